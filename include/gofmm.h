@@ -1,0 +1,198 @@
+/*
+ * gofmm.h -- C ABI of an MI355X (gfx950) evaluator for GOFMM compressions.
+ *
+ * GOFMM (Yu, Levitt, Reiz, Biros, "Geometry-Oblivious FMM for Compressing
+ * Dense SPD Matrices", SC'17) approximates a dense SPD matrix K by a
+ * hierarchical matrix K~ = D + S + UV (Sec. 1, eq. hmatrix) built only from a
+ * routine that returns blocks K(I, J) (Sec. 1, problem statement), and then
+ * multiplies K~ by a block W of r right-hand sides (Sec. 2.2, Alg. Evaluate).
+ *
+ * This library builds the compression on the host (ball tree, neighbours,
+ * interaction lists, interpolative decompositions, cached blocks) and
+ * evaluates U = K~ W on the GPU with hand-written HIP kernels.
+ *
+ * Conventions for every call:
+ *   - return 0 on success, a negative GOFMM_E* code on failure; the failing
+ *     call's message is available from gofmm_last_error() on the same thread;
+ *   - on failure no handle is produced and nothing leaks;
+ *   - all index arrays use the caller's original (unpermuted) numbering;
+ *   - device pointers are HIP device addresses on the current device; the
+ *     caller owns W, U and the stream; the library owns every byte of a
+ *     compression, host and device, until gofmm_free.
+ */
+#ifndef GOFMM_H
+#define GOFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+enum {
+  GOFMM_OK = 0,
+  GOFMM_EINVAL = -1,     /* bad argument (n <= 0, m < 1, s < 1, tau < 0,
+                            budget outside [0,1], null pointer, bad ld) */
+  GOFMM_ECALLBACK = -2,  /* the sampler returned non-zero */
+  GOFMM_ENOTSPD = -3,    /* K_ii <= 0 or a non-finite entry */
+  GOFMM_ENOMEM = -4,     /* host or device allocation failed */
+  GOFMM_EHIP = -5,       /* a HIP runtime error (message in last_error) */
+  GOFMM_EIO = -6,        /* file could not be read or written / bad format */
+  GOFMM_ELIMIT = -7      /* a documented size limit was exceeded */
+};
+
+/* distance used for the tree and the neighbours (Sec. 2.1) */
+enum { GOFMM_GRAM_L2 = 0,   /* d_ij^2 = K_ii + K_jj - 2 K_ij  (eq. 3) */
+       GOFMM_ANGLE = 1 };   /* d_ij = 1 - K_ij^2 / (K_ii K_jj) (eq. 4) */
+
+/* storage precision of the device operator; accumulation is always FP32 */
+enum { GOFMM_FP32 = 0,      /* FP32 storage, FP32 matrix-core products */
+       GOFMM_BF16 = 1,      /* BF16 storage; right-hand operands rounded to BF16 */
+       GOFMM_BF16X3 = 2 };  /* split BF16 (hi + lo) for both operands, three
+                               BF16 products per step; near-FP32 accuracy */
+
+typedef struct gofmm_compression gofmm_compression;   /* opaque */
+
+/*
+ * Entry sampler: the method's only input (Sec. 1, problem statement).
+ * Fill out[i * ld + j] = K(I[i], J[j]) in FP64 (row-major, ld >= nJ) for
+ * original indices I[0..nI), J[0..nJ).  K must be symmetric (K(i,j) == K(j,i)
+ * bitwise) and positive definite.  Called only inside gofmm_compress and
+ * gofmm_import, possibly from several threads at once (params.threads).
+ * Return 0; any other value aborts the call with GOFMM_ECALLBACK.
+ */
+typedef int (*gofmm_sampler)(void* user, int64_t nI, const int64_t* I,
+                             int64_t nJ, const int64_t* J, double* out, int64_t ld);
+
+/*
+ * Method parameters (Sec. 3, parameter selection): m, s, tau, kappa, budget,
+ * distance.  Fill with gofmm_default_params and override.
+ */
+typedef struct {
+  int64_t leaf_size;        /* m: leaves hold at most m indices */
+  int64_t max_rank;         /* s: cap on every skeleton rank */
+  double tol;               /* tau: adaptive-rank tolerance, relative to |R_00|
+                               of the pivoted QR of the sampled block */
+  int32_t kappa;            /* neighbours per index (an index is its own first) */
+  double budget;            /* near-field budget: each leaf keeps at most
+                               floor(budget * N / m) other leaves (eq. budget);
+                               0 gives the HSS form */
+  int32_t distance;         /* GOFMM_GRAM_L2 | GOFMM_ANGLE */
+  int32_t storage;          /* precision of P and coupling blocks K(b~, a~) */
+  int32_t near_storage;     /* precision of the near blocks K(b, a) */
+  uint64_t seed;            /* all random choices derive from it */
+  int32_t threads;          /* host threads for compression (0 = all) */
+  int32_t ann_max_iters;    /* randomized trees for the neighbour search (10) */
+  double ann_target_recall; /* stop the neighbour search at this recall (0.8) */
+  int32_t exact_knn;        /* 1: brute-force neighbours instead (small N) */
+} gofmm_params;
+
+/* Summary of a built compression (for flop/byte accounting and reports). */
+typedef struct {
+  int64_t n, depth, n_leaves, n_nodes;
+  int64_t rank_sum, rank_max;           /* over non-root nodes */
+  int64_t near_pairs, far_pairs;        /* ordered (leaf, leaf) / (node, node) */
+  double flops_per_rhs;                 /* Table 2 flops of one K~w, all phases */
+  double flops_phase[4];                /* per rhs: N2S, S2S, S2N, L2L */
+  int64_t operator_bytes;               /* device operator (all precisions held) */
+  int64_t operator_bytes_phase[4];      /* bytes read per evaluate, by phase */
+  int64_t workspace_rows;               /* rows of the r-wide skeleton workspace */
+} gofmm_stats_t;
+
+/* Defaults: m 256, s 256, tau 1e-5, kappa 32, budget 0.03, Gram-l2, FP32. */
+void gofmm_default_params(gofmm_params* p);
+
+/*
+ * Build a compression of the n x n matrix behind `sampler` (Alg. Compress):
+ * diagonal, randomized-tree neighbour search, metricSplit ball tree (Alg. 1),
+ * LeafNear with the budget ballot (Alg. 2), FindFar / MergeFar (Alg. 3, 4)
+ * with a symmetric refinement, nested IDs in FP64 (eqs. 7-8, Alg. 5), and the
+ * cached blocks Kba / SKba packed for the device in the requested precision.
+ * Host only: no GPU is touched until gofmm_prepare or the first evaluate.
+ */
+int gofmm_compress(int64_t n, gofmm_sampler sampler, void* user,
+                   const gofmm_params* params, gofmm_compression** out);
+
+/*
+ * Load the structure (tree, permutation, lists, skeletons, P) written by
+ * gofmm_export or by an external tool in the same format, and sample the
+ * cached blocks with `sampler`.  params supplies storage precisions and
+ * threads only; the method parameters come from the file.
+ */
+int gofmm_import(const char* path, gofmm_sampler sampler, void* user,
+                 const gofmm_params* params, gofmm_compression** out);
+
+/* Write the structure of a compression (no kernel blocks) to `path`. */
+int gofmm_export(const gofmm_compression* c, const char* path);
+
+/*
+ * Upload the operator to the current HIP device and size the workspace for
+ * up to r_max right-hand sides.  Synchronous.  Called implicitly by the
+ * first evaluate with the r of that call if not called before.
+ */
+int gofmm_prepare(gofmm_compression* c, int64_t r_max);
+
+/*
+ * U = K~ W (Alg. Evaluate: N2S, S2S, S2N, L2L).  W and U are device arrays
+ * of n rows in the original order, row-major with leading dimensions ldw,
+ * ldu >= r (FP32), and must not overlap.  Every row of U is overwritten.
+ * Work is enqueued on `hip_stream` (NULL = default stream) and the call
+ * returns without synchronizing.  Concurrent evaluates of one compression
+ * must be serialized by the caller (they share its workspace).  r == 0 is a
+ * no-op; r > r_max of a previous prepare grows the workspace synchronously.
+ */
+int gofmm_evaluate(gofmm_compression* c, int64_t r,
+                   const float* W, int64_t ldw, float* U, int64_t ldu,
+                   void* hip_stream);
+
+/*
+ * Same product as gofmm_evaluate, after timing every tile configuration of
+ * every launch for this r and keeping the fastest (later evaluates with the
+ * same r reuse the choice).  Synchronizes the stream.
+ */
+int gofmm_autotune(gofmm_compression* c, int64_t r,
+                   const float* W, int64_t ldw, float* U, int64_t ldu,
+                   void* hip_stream);
+
+/*
+ * k independent products U_i = K~_i W_i in one persistent launch: a single
+ * grid walks the union of all instances' tiles, with per-instance level
+ * counters ordering the upward and downward passes.  Same argument rules as
+ * gofmm_evaluate, per instance.  The k compressions must be distinct.
+ */
+int gofmm_evaluate_batched(int32_t k, gofmm_compression* const* c, const int64_t* r,
+                           const float* const* W, const int64_t* ldw,
+                           float* const* U, const int64_t* ldu, void* hip_stream);
+
+/* Device bytes a prepared compression holds for r_max right-hand sides. */
+int gofmm_footprint(const gofmm_compression* c, int64_t r_max, int64_t* bytes);
+
+/* Fill `out` with the summary of c. */
+int gofmm_stats(const gofmm_compression* c, gofmm_stats_t* out);
+
+/* Release a compression (host and device).  NULL is ignored. */
+void gofmm_free(gofmm_compression* c);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* gofmm_last_error(void);
+
+/* ------------------------------------------------ synthetic kernel sampler
+ * A ready-made thread-safe sampler for radial kernels over a point cloud the
+ * library copies and keeps hidden from the method:
+ *   kind 0  exp(-|x - y|^2 / (2 h^2))       (Gaussian)
+ *   kind 1  1 / sqrt(1 + |x - y|^2 / h^2)   (inverse multiquadric)
+ *   kind 2  1 / (|x - y| + 0.05)            (Laplacian-like)
+ * plus shift on the diagonal.  points: n x dim row-major FP64 (host).
+ * Pass gofmm_kernel_sample as the sampler and *state as its user pointer.
+ */
+int gofmm_kernel_create(int32_t kind, int64_t n, int32_t dim, const double* points,
+                        double h, double shift, void** state);
+int gofmm_kernel_sample(void* state, int64_t nI, const int64_t* I,
+                        int64_t nJ, const int64_t* J, double* out, int64_t ld);
+void gofmm_kernel_free(void* state);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GOFMM_H */

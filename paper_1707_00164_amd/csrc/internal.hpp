@@ -1,0 +1,157 @@
+// Internal declarations shared by the host compression, the packer, the file
+// format and the device evaluator.  Not part of the public ABI.
+#pragma once
+
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/gofmm.h"
+
+namespace gofmm {
+
+using i64 = int64_t;
+using i32 = int32_t;
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Error(code, msg); }
+void set_last_error(const std::string& msg);
+
+// ------------------------------------------------------------------ RNG
+// SplitMix64 (Steele, Lea, Flood 2014): a counter-based 64-bit generator.
+struct Rng {
+  uint64_t s;
+  explicit Rng(uint64_t seed) : s(seed) {}
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  // uniform integer in [0, n)
+  uint64_t below(uint64_t n) { return n ? next() % n : 0; }
+};
+inline uint64_t mix(uint64_t a, uint64_t b) { Rng r(a ^ (b * 0xD1B54A32D192ED03ull)); r.next(); return r.next(); }
+
+// ------------------------------------------------------------------ heap tree
+inline i64 n_nodes(int depth) { return (i64(1) << (depth + 1)) - 1; }
+inline i64 first_leaf(int depth) { return (i64(1) << depth) - 1; }
+inline int level_of(i64 h) { int l = 0; while (((h + 1) >> (l + 1)) != 0) ++l; return l; }
+
+// ------------------------------------------------------------------ sampler
+struct Sampler {
+  gofmm_sampler fn = nullptr;
+  void* user = nullptr;
+  // out: nI x nJ row-major with leading dimension ld (default nJ)
+  void operator()(i64 nI, const i64* I, i64 nJ, const i64* J, double* out, i64 ld = -1) const {
+    if (nI == 0 || nJ == 0) return;
+    int rc = fn(user, nI, I, nJ, J, out, ld < 0 ? nJ : ld);
+    if (rc != 0) fail(GOFMM_ECALLBACK, "sampler returned " + std::to_string(rc));
+  }
+};
+
+// ------------------------------------------------------------------ device plan
+enum Prec { PREC_F32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
+
+// One gather-GEMM: out[m x r] (=|+=) A[m x k] * B[k x r], where row t of B is
+// row rows[idx_off + t] of the right-hand-side space and row i of out is row
+// rows[idx_off + lda + i] of the output space (row codes below).
+struct TaskDesc {
+  i64 a_off;    // element offset of A (row-major, leading dim lda) in its buffer
+  i64 idx_off;  // offset into the row-code array
+  i32 m, k, lda, node;
+};
+
+// Row codes: c >= 0 is row c of the caller's W (reads) or U (writes);
+// c < 0 (and not ROW_ZERO) is workspace row -c-1; ROW_ZERO reads as zeros.
+constexpr i32 ROW_ZERO = INT32_MIN;
+
+enum Phase { PH_N2S = 0, PH_S2S = 1, PH_S2N = 2, PH_L2L = 3 };
+
+struct LaunchDesc {
+  int prec;          // Prec of A for every task in the range
+  int accumulate;    // 1: out += A B ; 0: out = A B
+  i32 t_begin, t_end;
+  int kind;          // 0 n2s-leaf, 1 n2s-level, 2 s2s(+s2n)-level, 3 leaf-out, 4 s2n-leaf, 5 l2l
+  int level;
+  std::string name;
+};
+
+struct HostPlan {
+  std::vector<TaskDesc> tasks;
+  std::vector<LaunchDesc> launches;
+  std::vector<i32> rows;
+  std::vector<float> a_f32;
+  std::vector<uint16_t> a_b16;
+  std::vector<uint16_t> a_x3hi, a_x3lo;
+  i64 ws_rows = 0;        // 2 * sum of ranks: skeleton weights then potentials
+  double flops_phase[4] = {0, 0, 0, 0};     // per right-hand side
+  i64 bytes_phase[4] = {0, 0, 0, 0};        // operator bytes read per evaluate
+};
+
+struct DeviceState;  // defined by the evaluator
+void device_state_free(DeviceState* d);
+
+// ------------------------------------------------------------------ compression
+struct Compression {
+  // parameters
+  i64 n = 0;
+  int depth = 0;
+  i64 leaf_size = 0, max_rank = 0;
+  double tol = 0;
+  int kappa = 0;
+  double budget = 0;
+  int distance = GOFMM_GRAM_L2;
+  int storage = GOFMM_FP32, near_storage = GOFMM_FP32;
+  uint64_t seed = 0;
+  // tree
+  std::vector<i64> perm, node_start, node_size, split_p, split_q;
+  std::vector<std::vector<i64>> centroid;
+  // neighbours (n x kappa, original numbering); may be empty after import
+  std::vector<i64> knn;
+  int knn_k = 0;
+  // lists
+  std::vector<std::vector<i64>> near;  // per leaf number, heap ids of leaves
+  std::vector<std::vector<i64>> far;   // per heap id
+  // skeletons
+  std::vector<std::vector<i64>> skel, samp;
+  std::vector<std::vector<double>> proj;  // s x ncols row-major
+  // device operator
+  HostPlan plan;
+  DeviceState* dev = nullptr;
+
+  i64 nn() const { return n_nodes(depth); }
+  i64 fl() const { return first_leaf(depth); }
+  i64 n_leaves() const { return i64(1) << depth; }
+  bool is_leaf(i64 h) const { return h >= fl(); }
+  i64 rank(i64 h) const { return (i64)skel[h].size(); }
+  i64 ncols(i64 h) const { return is_leaf(h) ? node_size[h] : rank(2 * h + 1) + rank(2 * h + 2); }
+  ~Compression() { if (dev) device_state_free(dev); }
+};
+
+// host pipeline pieces
+int choose_depth(i64 n, i64 m);
+void build_compression(Compression& c, const Sampler& K, const gofmm_params& p);
+void build_plan(Compression& c, const Sampler& K, int threads);
+void validate_structure(const Compression& c);
+void write_file(const Compression& c, const char* path);
+void read_file(Compression& c, const char* path);
+
+// FP64 ID of a row-major nrow x ncol block A (overwritten): returns rank s and
+// fills piv (ncol entries, first s are the skeleton columns) and P (s x ncol).
+int interp_decomp(double* A, int nrow, int ncol, double tol, int smax,
+                  std::vector<int>& piv, std::vector<double>& P);
+
+// BF16 round-to-nearest-even of a double (through its nearest float).
+uint16_t to_bf16(double x);
+double from_bf16(uint16_t h);
+
+}  // namespace gofmm

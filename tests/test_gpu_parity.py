@@ -1,0 +1,184 @@
+"""GPU K~W against the FP64 oracle on the same compression (through the C ABI).
+
+Tolerance (FP32 storage): the Frobenius relative error |U_gpu - U_ref| /
+|U_ref| must be <= 1e-5, and every element must satisfy
+|U_gpu - U_ref| <= 1e-5 * max|U_ref|.  Split-BF16 (about 16 significant bits
+per operand, relative representation error <= 2^-17) is held to 3e-5
+Frobenius and 1e-4 per element; plain BF16 (8 bits) to 2e-2 Frobenius.  U_ref is the oracle's FP64 tree walk
+of the exported structure, applied to the same FP32-rounded W, with every
+kernel block re-sampled by the oracle from its own kernel.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import cuda_rhs, export_read, log, rel_err
+from oracle import cfile, compress as ocompress, evaluate, kernels
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "no GPU"
+    import paper_1707_00164_amd as g
+    g.lib()
+    return t
+
+
+def _sampler(pts, kind, h, shift):
+    import paper_1707_00164_amd as g
+    return g.KernelSampler(pts, kind, h, shift)
+
+
+TOL_X3_F, TOL_X3_E = 3e-5, 1e-4
+
+
+def _check(U_gpu, U_ref, tol=TOL, what="", tol_elem=None):
+    U_gpu = np.asarray(U_gpu, dtype=np.float64)
+    e = rel_err(U_gpu, U_ref)
+    emax = float(np.max(np.abs(U_gpu - U_ref)) / np.max(np.abs(U_ref)))
+    log(f"  {what}: rel_F={e:.3e} max_elem_rel={emax:.3e}")
+    assert np.all(np.isfinite(U_gpu))
+    assert e <= tol and emax <= (tol if tol_elem is None else tol_elem), (e, emax)
+
+
+def _run(torch, comp, K, n, r, seed, ld=None):
+    W64, Wd = cuda_rhs(n, r, seed, ld)
+    Ud = comp.evaluate(Wd)
+    torch.cuda.synchronize()
+    cc = export_read(comp)
+    W32 = Wd.cpu().numpy().astype(np.float64)
+    return Ud.cpu().numpy(), evaluate.tree_walk(cc, K, W32)
+
+
+def test_small_gaussian_hss_fp32(torch):
+    import paper_1707_00164_amd as g
+    w = workloads.small_gaussian()
+    log(f"case {w.name} r={w.r}")
+    pts = workloads.points(w)
+    S = _sampler(pts, w.kernel, w.h, w.shift)
+    comp = g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol,
+                                  kappa=w.kappa, budget=w.budget, seed=11)
+    K = kernels.KernelMatrix(pts, w.kernel, w.h, w.shift)
+    U, ref = _run(torch, comp, K, w.n, w.r, w.seed)
+    _check(U, ref, what=w.name)
+
+
+@pytest.mark.parametrize("r", [1, 7, 33, 130])
+def test_fmm_ragged_fp32(torch, r):
+    import paper_1707_00164_amd as g
+    rng = np.random.default_rng(4)
+    n = 3001
+    pts = rng.random((n, 3))
+    log(f"case fmm_ragged n={n} r={r}")
+    S = _sampler(pts, "gaussian", 0.3, 1e-3)
+    comp = g.Compression.compress(S, leaf_size=100, max_rank=64, tol=1e-6, kappa=16, budget=0.1, seed=5)
+    st = comp.stats()
+    assert st.depth == 5 and st.far_pairs > 62                 # an FMM (not HSS) structure
+    K = kernels.KernelMatrix(pts, "gaussian", 0.3, 1e-3)
+    U, ref = _run(torch, comp, K, n, r, 100 + r)
+    _check(U, ref, what=f"fmm_ragged r={r}")
+
+
+def test_strided_operands(torch):
+    import paper_1707_00164_amd as g
+    rng = np.random.default_rng(5)
+    n = 1500
+    pts = rng.random((n, 2))
+    log("case strided ld=50 r=37")
+    S = _sampler(pts, "imq", 0.3, 1e-2)
+    comp = g.Compression.compress(S, leaf_size=64, max_rank=40, tol=1e-5, kappa=8, budget=0.05, seed=6)
+    K = kernels.KernelMatrix(pts, "imq", 0.3, 1e-2)
+    W64, Wd = cuda_rhs(n, 37, 9, ld=50)
+    Ubig = torch.full((n, 41), float("nan"), device="cuda")
+    U = Ubig[:, :37]
+    comp.evaluate(Wd, U)
+    torch.cuda.synchronize()
+    assert torch.isnan(Ubig[:, 37:]).all()                       # untouched beyond r
+    ref = evaluate.tree_walk(export_read(comp), K, Wd.cpu().numpy().astype(np.float64))
+    _check(U.cpu().numpy(), ref, what="strided")
+
+
+def test_oracle_compression_imported(torch):
+    """The oracle's own compression, loaded by the library, evaluated on GPU."""
+    import os
+    import tempfile
+    import paper_1707_00164_amd as g
+    rng = np.random.default_rng(6)
+    n = 2000
+    pts = rng.random((n, 3))
+    log("case oracle-built compression n=2000")
+    K = kernels.KernelMatrix(pts, "laplace_like", 1.0, 1e-2)
+    oc = ocompress.compress(K, n, leaf_size=64, max_rank=48, tol=1e-5, kappa=16, budget=0.05, seed=2)
+    fd, path = tempfile.mkstemp(suffix=".gofmm")
+    os.close(fd)
+    try:
+        cfile.write(oc, path)
+        S = _sampler(pts, "laplace_like", 1.0, 1e-2)
+        comp = g.Compression.load(path, S)
+    finally:
+        os.unlink(path)
+    W64, Wd = cuda_rhs(n, 24, 3)
+    U = comp.evaluate(Wd)
+    torch.cuda.synchronize()
+    ref = evaluate.tree_walk(oc, K, Wd.cpu().numpy().astype(np.float64))
+    _check(U.cpu().numpy(), ref, what="imported")
+
+
+@pytest.mark.parametrize("n,m", [(100, 128), (300, 150), (129, 128)])
+def test_shallow_trees(torch, n, m):
+    import paper_1707_00164_amd as g
+    rng = np.random.default_rng(n)
+    pts = rng.random((n, 3))
+    log(f"case shallow n={n} m={m}")
+    S = _sampler(pts, "gaussian", 0.5, 1e-3)
+    comp = g.Compression.compress(S, leaf_size=m, max_rank=32, tol=1e-6, kappa=8, budget=0.0, seed=1)
+    K = kernels.KernelMatrix(pts, "gaussian", 0.5, 1e-3)
+    U, ref = _run(torch, comp, K, n, 5, 1)
+    _check(U, ref, what=f"shallow n={n}")
+
+
+def test_r_zero_is_noop(torch):
+    import paper_1707_00164_amd as g
+    pts = np.random.default_rng(0).random((200, 2))
+    comp = g.Compression.compress(_sampler(pts, "gaussian", 0.5, 1e-3), leaf_size=32, max_rank=16,
+                                  tol=1e-4, kappa=8, budget=0.0)
+    W = torch.zeros((200, 0), device="cuda")
+    comp.evaluate(W)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("storage,tol", [("bf16x3", TOL_X3_F), ("bf16", 2e-2)])
+def test_mixed_precision_error_stated(torch, storage, tol):
+    import paper_1707_00164_amd as g
+    prec = {"bf16": g.BF16, "bf16x3": g.BF16X3}[storage]
+    w = workloads.small_gaussian()
+    pts = workloads.points(w)
+    log(f"case {w.name} storage={storage}")
+    S = _sampler(pts, w.kernel, w.h, w.shift)
+    comp = g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol,
+                                  kappa=w.kappa, budget=0.05, seed=11, storage=prec, near_storage=prec)
+    K = kernels.KernelMatrix(pts, w.kernel, w.h, w.shift)
+    U, ref = _run(torch, comp, K, w.n, 64, w.seed)
+    e = rel_err(U, ref)
+    log(f"  storage={storage}: rel_F={e:.3e} (stated bound {tol})")
+    assert e <= tol
+
+
+def test_mixed_near_fp32_far_bf16(torch):
+    """P and coupling in BF16, near blocks FP32: split leaf launches."""
+    import paper_1707_00164_amd as g
+    w = workloads.small_gaussian()
+    pts = workloads.points(w)
+    log("case split leaf launches")
+    S = _sampler(pts, w.kernel, w.h, w.shift)
+    comp = g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol,
+                                  kappa=w.kappa, budget=0.05, seed=11, storage=g.BF16X3,
+                                  near_storage=g.FP32)
+    K = kernels.KernelMatrix(pts, w.kernel, w.h, w.shift)
+    U, ref = _run(torch, comp, K, w.n, 20, w.seed)
+    _check(U, ref, tol=TOL_X3_F, tol_elem=TOL_X3_E, what="x3 far / fp32 near")
