@@ -165,6 +165,26 @@ int gofmm_evaluate_batched(int32_t k, gofmm_compression* const* c, const int64_t
                            const float* const* W, const int64_t* ldw,
                            float* const* U, const int64_t* ldu, void* hip_stream);
 
+/*
+ * Launches of one evaluate, in order.  For launch i: its name (e.g. "n2s_leaf",
+ * "s2s_l3", "leaf"), the Table 2 flops it performs per right-hand side, and
+ * the operator bytes it reads.  name receives at most name_len bytes
+ * including the terminator.
+ */
+int gofmm_launch_count(const gofmm_compression* c, int32_t* count);
+int gofmm_launch_info(const gofmm_compression* c, int32_t i, char* name, int32_t name_len,
+                      double* flops_per_rhs, int64_t* operator_bytes);
+
+/*
+ * Per-launch timing.  While enabled, every evaluate of c records a HIP event
+ * before and after each of its launches on the evaluation stream (no extra
+ * synchronization).  gofmm_profile_read waits for the recorded events, writes
+ * for each launch i < n the summed milliseconds and the number of recorded
+ * launches, and clears the records.
+ */
+int gofmm_profile(gofmm_compression* c, int32_t enable);
+int gofmm_profile_read(gofmm_compression* c, int32_t n, float* total_ms, int32_t* calls);
+
 /* Device bytes a prepared compression holds for r_max right-hand sides. */
 int gofmm_footprint(const gofmm_compression* c, int64_t r_max, int64_t* bytes);
 

@@ -17,6 +17,8 @@ void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
 void device_evaluate_batched(int k, Compression* const* c, const i64* r, const float* const* W,
                              const i64* ldw, float* const* U, const i64* ldu, void* stream);
 i64 device_footprint(const Compression& c, i64 r_max);
+void device_profile(Compression& c, int on);
+void device_profile_read(Compression& c, int n, float* total_ms, int* calls);
 
 }  // namespace gofmm
 
@@ -173,6 +175,42 @@ extern "C" int gofmm_evaluate_batched(int32_t k, gofmm_compression* const* c, co
       cs[i] = &c[i]->c;
     }
     device_evaluate_batched(k, cs.data(), r, W, ldw, U, ldu, hip_stream);
+  });
+}
+
+extern "C" int gofmm_launch_count(const gofmm_compression* c, int32_t* count) {
+  return guarded([&] {
+    if (!c || !count) fail(GOFMM_EINVAL, "NULL argument");
+    *count = (int32_t)c->c.plan.launches.size();
+  });
+}
+
+extern "C" int gofmm_launch_info(const gofmm_compression* c, int32_t i, char* name, int32_t name_len,
+                                 double* flops_per_rhs, int64_t* operator_bytes) {
+  return guarded([&] {
+    if (!c) fail(GOFMM_EINVAL, "NULL compression");
+    if (i < 0 || i >= (int32_t)c->c.plan.launches.size()) fail(GOFMM_EINVAL, "launch index out of range");
+    const LaunchDesc& l = c->c.plan.launches[i];
+    if (name && name_len > 0) {
+      std::strncpy(name, l.name.c_str(), (size_t)name_len - 1);
+      name[name_len - 1] = 0;
+    }
+    if (flops_per_rhs) *flops_per_rhs = l.flops;
+    if (operator_bytes) *operator_bytes = l.bytes;
+  });
+}
+
+extern "C" int gofmm_profile(gofmm_compression* c, int32_t enable) {
+  return guarded([&] {
+    if (!c) fail(GOFMM_EINVAL, "NULL compression");
+    device_profile(c->c, enable);
+  });
+}
+
+extern "C" int gofmm_profile_read(gofmm_compression* c, int32_t n, float* total_ms, int32_t* calls) {
+  return guarded([&] {
+    if (!c || (n > 0 && (!total_ms || !calls))) fail(GOFMM_EINVAL, "NULL argument");
+    device_profile_read(c->c, n, total_ms, calls);
   });
 }
 

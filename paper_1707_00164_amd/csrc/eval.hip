@@ -20,280 +20,48 @@
 //           a_hi b_hi + a_hi b_lo + a_lo b_hi, with x = hi + lo, hi = bf16(x),
 //           lo = bf16(x - hi): about 16 significant bits per operand.
 //
-// Accumulation is FP32 in the matrix-core accumulators.  Block ids are
-// remapped so that consecutive tiles (same A rows, neighbouring columns) run
-// on the same XCD and share its L2.
+// Accumulation is FP32 in the matrix-core accumulators.  This file holds the
+// host side: device buffers, work-item lists and launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
-#include "internal.hpp"
+#include "kernels.hpp"
 
 namespace gofmm {
 
-// ------------------------------------------------------------------ device code
-namespace dev {
-
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-
-constexpr int BK = 32;
-constexpr int NT = 256;
-
-struct KArgs {
-  const TaskDesc* tasks;
-  const int2* tiles;    // (task, m-tile) entries
-  int total;            // entries * ntn work items
-  int ntn;              // column tiles
-  const void* A;
-  long long plane;      // offset of the lo plane (split BF16)
-  const int* rows;
-  const float* W;
-  long long ldw;
-  float* U;
-  long long ldu;
-  float* WS;
-  long long ldws;
-  int r;
-  int vec;              // rows of W, U, WS are 16-byte aligned
-};
-
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned int u = __builtin_bit_cast(unsigned int, f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_val(unsigned short h) {
-  return __builtin_bit_cast(float, (unsigned int)h << 16);
-}
-
-template <int PREC, int BM, int BN, int WM, int WN, bool ACC>
-__global__ __launch_bounds__(NT) void gemm_tiles(KArgs a) {
-  constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 32, TN = WTN / 32;
-  static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "tile shape");
-  constexpr bool F32 = PREC == PREC_F32;
-  constexpr bool X3 = PREC == PREC_BF16X3;
-  constexpr int NPL = X3 ? 2 : 1;                    // planes per operand
-  constexpr int LDK = F32 ? BK + 4 : BK + 8;         // LDS row stride (elements)
-  using E = typename std::conditional<F32, float, unsigned short>::type;
-  __shared__ __attribute__((aligned(16))) E sA[NPL * BM * LDK];
-  __shared__ __attribute__((aligned(16))) E sB[NPL * BN * LDK];
-  __shared__ int sOut[BM];
-
-  const int G = gridDim.x;                           // a multiple of 8
-  const int lid = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-  if (lid >= a.total) return;
-  const int2 tl = a.tiles[lid / a.ntn];
-  const int n0 = (lid % a.ntn) * BN;
-  const TaskDesc td = a.tasks[tl.x];
-  const int m0 = tl.y * BM;
-  const int tid = threadIdx.x;
-  const int* codes = a.rows + td.idx_off;
-  for (int i = tid; i < BM; i += NT) sOut[i] = (m0 + i < td.m) ? codes[td.lda + m0 + i] : ROW_ZERO;
-
-  constexpr int EPU = F32 ? 4 : 8;                   // A elements per 16-byte unit
-  constexpr int AU = BM * BK / EPU, AUT = (AU + NT - 1) / NT;
-  constexpr int BU = BK * BN / 4, BUT = (BU + NT - 1) / NT;
-  uint4 ra[NPL][AUT];
-  f32x4 rb[BUT];
-  const E* Ab = reinterpret_cast<const E*>(a.A);
-
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int t = 0; t < AUT; ++t) {
-      const int u = tid + t * NT;
-      if (u < AU) {
-        const int row = u / (BK / EPU), c = u % (BK / EPU);
-        if (m0 + row < td.m) {
-          const long long off = td.a_off + (long long)(m0 + row) * td.lda + k0 + c * EPU;
-          ra[0][t] = *reinterpret_cast<const uint4*>(Ab + off);
-          if constexpr (X3) ra[NPL - 1][t] = *reinterpret_cast<const uint4*>(Ab + a.plane + off);
-        } else {
-#pragma unroll
-          for (int p = 0; p < NPL; ++p) ra[p][t] = make_uint4(0, 0, 0, 0);
-        }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < BUT; ++t) {
-      const int u = tid + t * NT;
-      if (u < BU) {
-        const int krow = u / (BN / 4), c4 = u % (BN / 4);
-        const int code = codes[k0 + krow];
-        const int col = n0 + 4 * c4;
-        f32x4 v = {0.f, 0.f, 0.f, 0.f};
-        if (code != ROW_ZERO) {
-          const float* p = code >= 0 ? a.W + (long long)code * a.ldw
-                                     : a.WS + (long long)(-(code + 1)) * a.ldws;
-          if (a.vec && col + 3 < a.r) {
-            v = *reinterpret_cast<const f32x4*>(p + col);
-          } else {
-            if (col < a.r) v[0] = p[col];
-            if (col + 1 < a.r) v[1] = p[col + 1];
-            if (col + 2 < a.r) v[2] = p[col + 2];
-            if (col + 3 < a.r) v[3] = p[col + 3];
-          }
-        }
-        rb[t] = v;
-      }
-    }
-  };
-
-  auto lstore = [&]() {
-#pragma unroll
-    for (int t = 0; t < AUT; ++t) {
-      const int u = tid + t * NT;
-      if (u < AU) {
-        const int row = u / (BK / EPU), c = u % (BK / EPU);
-#pragma unroll
-        for (int p = 0; p < NPL; ++p)
-          *reinterpret_cast<uint4*>(&sA[p * BM * LDK + row * LDK + c * EPU]) = ra[p][t];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < BUT; ++t) {
-      const int u = tid + t * NT;
-      if (u < BU) {
-        const int krow = u / (BN / 4), c4 = u % (BN / 4);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int idx = (4 * c4 + e) * LDK + krow;
-          if constexpr (F32) {
-            sB[idx] = rb[t][e];
-          } else {
-            const unsigned short hi = bf16_rne(rb[t][e]);
-            sB[idx] = hi;
-            if constexpr (X3) sB[BN * LDK + idx] = bf16_rne(rb[t][e] - bf16_val(hi));
-          }
-        }
-      }
-    }
-  };
-
-  const int lane = tid & 63, li = lane & 31, lh = lane >> 5;
-  const int wid = tid >> 6, wr = wid / WN, wc = wid % WN;
-  f32x16 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
-
-  auto compute = [&]() {
-    if constexpr (F32) {
-      // lane (li, lh) feeds k = lh * 16 + 4u + q: the two halves of the wave
-      // cover k 0..15 and 16..31 of the slab, matching A and B.
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        f32x4 av[TM], bv[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-          av[i] = *reinterpret_cast<const f32x4*>(&sA[(wr * WTM + i * 32 + li) * LDK + lh * 16 + 4 * u]);
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          bv[j] = *reinterpret_cast<const f32x4*>(&sB[(wc * WTN + j * 32 + li) * LDK + lh * 16 + 4 * u]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][q], bv[j][q], acc[i][j], 0, 0, 0);
-      }
-    } else {
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        bf16x8 ah[TM], bh[TN], al[TM], bl[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          const int o = (wr * WTM + i * 32 + li) * LDK + 16 * s + 8 * lh;
-          ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sA[o]));
-          if constexpr (X3) al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sA[BM * LDK + o]));
-        }
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          const int o = (wc * WTN + j * 32 + li) * LDK + 16 * s + 8 * lh;
-          bh[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sB[o]));
-          if constexpr (X3) bl[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sB[BN * LDK + o]));
-        }
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            if constexpr (X3) {
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-            }
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-          }
-      }
-    }
-  };
-
-  const int nk = td.lda / BK;
-  if (nk > 0) gload(0);
-  for (int kt = 0; kt < nk; ++kt) {
-    __syncthreads();
-    lstore();
-    __syncthreads();
-    if (kt + 1 < nk) gload((kt + 1) * BK);
-    compute();
-  }
-  __syncthreads();
-
-  // epilogue: accumulator (i, j, v) of lane (li, lh) is row 8(v/4) + 4 lh + v%4,
-  // column li of the 32 x 32 block
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int row = wr * WTM + i * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
-      if (m0 + row >= td.m) continue;
-      const int code = sOut[row];
-      float* p = code >= 0 ? a.U + (long long)code * a.ldu : a.WS + (long long)(-(code + 1)) * a.ldws;
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int col = n0 + wc * WTN + j * 32 + li;
-        if (col < a.r) {
-          if constexpr (ACC) p[col] += acc[i][j][v];
-          else p[col] = acc[i][j][v];
-        }
-      }
-    }
-}
-
-}  // namespace dev
-
 // ------------------------------------------------------------------ configurations
-struct Cfg { int bm, bn; };
-static const Cfg kCfgs[] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}, {128, 32}, {32, 128}};
-constexpr int kNumCfg = sizeof(kCfgs) / sizeof(kCfgs[0]);
+using dev::Cfg;
+using dev::KernelFn;
+using dev::kCfgs;
+using dev::kNumCfg;
+using dev::kNumFamily;
 
-typedef void (*KernelFn)(dev::KArgs);
-
-template <int PREC, bool ACC>
-static KernelFn pick(int cfg) {
-  switch (cfg) {
-    case 0: return dev::gemm_tiles<PREC, 128, 128, 2, 2, ACC>;
-    case 1: return dev::gemm_tiles<PREC, 128, 64, 2, 2, ACC>;
-    case 2: return dev::gemm_tiles<PREC, 64, 128, 2, 2, ACC>;
-    case 3: return dev::gemm_tiles<PREC, 64, 64, 2, 2, ACC>;
-    case 4: return dev::gemm_tiles<PREC, 128, 32, 4, 1, ACC>;
-    default: return dev::gemm_tiles<PREC, 32, 128, 1, 4, ACC>;
-  }
+// family: 0 upward pass, 1 far field, 2 downward pass (accumulating),
+// 3 leaf output, 4 leaf output accumulating
+static int family_of(const LaunchDesc& l) {
+  if (l.kind == 0 || l.kind == 1) return 0;
+  if (l.kind == 2) return 1;
+  if (l.kind == 6) return 2;
+  return l.accumulate ? 4 : 3;
 }
 
-static KernelFn kernel_for(int prec, bool acc, int cfg) {
-  if (prec == PREC_F32) return acc ? pick<PREC_F32, true>(cfg) : pick<PREC_F32, false>(cfg);
-  if (prec == PREC_BF16) return acc ? pick<PREC_BF16, true>(cfg) : pick<PREC_BF16, false>(cfg);
-  return acc ? pick<PREC_BF16X3, true>(cfg) : pick<PREC_BF16X3, false>(cfg);
+static KernelFn kernel_for(const LaunchDesc& l, int cfg) {
+  static KernelFn tables[3][kNumCfg * kNumFamily];
+  static bool init = false;
+  if (!init) {
+    dev::kernels_f32(tables[PREC_F32]);
+    dev::kernels_bf16(tables[PREC_BF16]);
+    dev::kernels_x3(tables[PREC_BF16X3]);
+    init = true;
+  }
+  return tables[l.prec][cfg * kNumFamily + family_of(l)];
 }
 
 // ------------------------------------------------------------------ device state
@@ -307,9 +75,16 @@ struct DeviceState {
   i32* rows = nullptr;
   float* ws = nullptr;
   i64 ws_cols = 0;                  // floats per workspace row allocated
-  std::map<int, std::pair<int2*, int>> tiles;   // key launch * 256 + bm
-  std::map<long long, int> tuned;   // (launch, r) -> configuration
+  // work-item lists per (launch, configuration, column tiles)
+  std::map<std::tuple<int, int, int>, std::pair<int2*, int>> items;
+  std::map<std::pair<int, i64>, int> tuned;   // (launch, r) -> configuration
   i64 op_bytes = 0;
+  // per-launch timing (HIP events around every launch while enabled)
+  bool profiling = false;
+  std::vector<hipEvent_t> events;
+  size_t ev_used = 0;
+  struct Rec { int launch; hipEvent_t a, b; };
+  std::vector<Rec> pending;
 };
 
 #define HIP_OK(expr)                                                                 \
@@ -331,7 +106,8 @@ void device_state_free(DeviceState* d) {
   (void)hipFree(d->tasks);
   (void)hipFree(d->rows);
   (void)hipFree(d->ws);
-  for (auto& kv : d->tiles) (void)hipFree(kv.second.first);
+  for (auto& kv : d->items) (void)hipFree(kv.second.first);
+  for (auto& ev : d->events) (void)hipEventDestroy(ev);
   if (cur >= 0) (void)hipSetDevice(cur);
   delete d;
 }
@@ -385,22 +161,53 @@ void device_prepare(Compression& c, i64 r_max) {
   }
 }
 
-static std::pair<int2*, int> tiles_for(Compression& c, int li, int bm) {
-  DeviceState* d = c.dev;
-  const int key = li * 256 + bm;
-  auto it = d->tiles.find(key);
-  if (it != d->tiles.end()) return it->second;
-  const LaunchDesc& l = c.plan.launches[li];
-  std::vector<int2> t;
+constexpr int kXcds = 8;   // MI355X: blocks are dealt to the 8 XCDs round-robin by id
+
+// Work items of launch li for tile configuration cfg and ntn column tiles:
+// the (task, row tile) groups sorted by k (longest first) are assigned to the
+// least-loaded XCD; each group's ntn column tiles stay on that XCD (they
+// share the A rows), and block id b runs item b % 8's queue entry b / 8.
+static std::vector<int2> build_items(const HostPlan& pl, const LaunchDesc& l, int bm, int ntn) {
+  struct G { i32 task, mt; i64 cost; };
+  std::vector<G> groups;
   for (i32 k = l.t_begin; k < l.t_end; ++k)
-    for (int mt = 0; mt * bm < c.plan.tasks[k].m; ++mt) t.push_back(make_int2(k, mt));
-  int2* dp = nullptr;
-  if (!t.empty()) {
-    HIP_OK(hipMalloc((void**)&dp, t.size() * sizeof(int2)));
-    HIP_OK(hipMemcpy(dp, t.data(), t.size() * sizeof(int2), hipMemcpyHostToDevice));
+    for (int mt = 0; mt * bm < pl.tasks[k].m; ++mt)
+      groups.push_back({k, mt, (i64)std::max(pl.tasks[k].lda, 32)});
+  std::stable_sort(groups.begin(), groups.end(), [](const G& x, const G& y) { return x.cost > y.cost; });
+  std::vector<std::vector<int2>> q(kXcds);
+  std::vector<i64> load(kXcds, 0);
+  for (const G& g : groups) {
+    int best = 0;
+    for (int x = 1; x < kXcds; ++x)
+      if (load[x] < load[best]) best = x;
+    load[best] += g.cost * ntn;
+    for (int nt = 0; nt < ntn; ++nt) q[best].push_back(make_int2(g.task, (g.mt << 16) | nt));
   }
-  d->tiles[key] = {dp, (int)t.size()};
-  return d->tiles[key];
+  size_t len = 0;
+  for (auto& v : q) len = std::max(len, v.size());
+  std::vector<int2> items(len * kXcds, make_int2(-1, 0));
+  for (int x = 0; x < kXcds; ++x)
+    for (size_t j = 0; j < q[x].size(); ++j) items[j * kXcds + x] = q[x][j];
+  return items;
+}
+
+static std::pair<int2*, int> items_for(Compression& c, int li, int cfg, int ntn) {
+  DeviceState* d = c.dev;
+  const auto key = std::make_tuple(li, cfg, ntn);
+  auto it = d->items.find(key);
+  if (it != d->items.end()) return it->second;
+  if (ntn >= (1 << 16)) fail(GOFMM_ELIMIT, "too many column tiles");
+  const LaunchDesc& l = c.plan.launches[li];
+  for (i32 k = l.t_begin; k < l.t_end; ++k)
+    if ((c.plan.tasks[k].m + kCfgs[cfg].bm - 1) / kCfgs[cfg].bm >= (1 << 15)) fail(GOFMM_ELIMIT, "too many row tiles");
+  std::vector<int2> v = build_items(c.plan, l, kCfgs[cfg].bm, ntn);
+  int2* dp = nullptr;
+  if (!v.empty()) {
+    HIP_OK(hipMalloc((void**)&dp, v.size() * sizeof(int2)));
+    HIP_OK(hipMemcpy(dp, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice));
+  }
+  d->items[key] = {dp, (int)v.size()};
+  return d->items[key];
 }
 
 // Padded-work model: tile count x tile area x k, plus a per-tile overhead.
@@ -418,7 +225,6 @@ static int choose_cfg(const Compression& c, int li, i64 r) {
       cost += mt * nt * g.bm * g.bn * (double)std::max(t.lda, 32);
       tiles += mt * nt;
     }
-    // fewer work items than compute units leaves the chip idle
     const double fill = std::min(1.0, tiles / 256.0);
     cost = cost / fill + tiles * 32.0 * 128 * 128;
     if (cost < best) { best = cost; bc = q; }
@@ -435,40 +241,63 @@ struct EvalArgs {
   hipStream_t stream;
 };
 
-static void launch_all(Compression& c, const EvalArgs& e, int forced_cfg) {
+static bool make_args(Compression& c, int li, int cfg, const EvalArgs& e, dev::KArgs& a, int& grid) {
   DeviceState* d = c.dev;
-  const i64 ldws = ws_cols_for(e.r);
-  const bool vec = ((uintptr_t)e.W % 16 == 0) && ((uintptr_t)e.U % 16 == 0) && e.ldw % 4 == 0 &&
-                   e.ldu % 4 == 0;
+  const LaunchDesc& l = c.plan.launches[li];
+  const Cfg& g = kCfgs[cfg];
+  const int ntn = (int)((e.r + g.bn - 1) / g.bn);
+  auto it = items_for(c, li, cfg, ntn);
+  if (it.second == 0) return false;
+  a.tasks = d->tasks;
+  a.items = it.first;
+  a.A = l.prec == PREC_F32 ? (const void*)d->a_f32 : l.prec == PREC_BF16 ? (const void*)d->a_b16 : (const void*)d->a_x3;
+  a.plane = d->x3_plane;
+  a.rows = d->rows;
+  a.W = e.W;
+  a.ldw = e.ldw;
+  a.U = e.U;
+  a.ldu = e.ldu;
+  a.WS = d->ws;
+  a.ldws = ws_cols_for(e.r);
+  a.r = (int)e.r;
+  a.vec = ((uintptr_t)e.W % 16 == 0) && ((uintptr_t)e.U % 16 == 0) && e.ldw % 4 == 0 && e.ldu % 4 == 0;
+  grid = it.second;
+  return true;
+}
+
+static int cfg_for(Compression& c, int li, i64 r) {
+  auto it = c.dev->tuned.find({li, r});
+  return it != c.dev->tuned.end() ? it->second : choose_cfg(c, li, r);
+}
+
+static void launch_all(Compression& c, const EvalArgs& e) {
+  DeviceState* d = c.dev;
   for (int li = 0; li < (int)c.plan.launches.size(); ++li) {
     const LaunchDesc& l = c.plan.launches[li];
-    int cfg = forced_cfg;
-    if (cfg < 0) {
-      auto it = d->tuned.find((long long)li * (1ll << 32) + e.r);
-      cfg = it != d->tuned.end() ? it->second : choose_cfg(c, li, e.r);
-    }
-    const Cfg& g = kCfgs[cfg];
-    auto tl = tiles_for(c, li, g.bm);
-    if (tl.second == 0) continue;
+    const int cfg = cfg_for(c, li, e.r);
     dev::KArgs a;
-    a.tasks = d->tasks;
-    a.tiles = tl.first;
-    a.ntn = (int)((e.r + g.bn - 1) / g.bn);
-    a.total = tl.second * a.ntn;
-    a.A = l.prec == PREC_F32 ? (const void*)d->a_f32 : l.prec == PREC_BF16 ? (const void*)d->a_b16 : (const void*)d->a_x3;
-    a.plane = d->x3_plane;
-    a.rows = d->rows;
-    a.W = e.W;
-    a.ldw = e.ldw;
-    a.U = e.U;
-    a.ldu = e.ldu;
-    a.WS = d->ws;
-    a.ldws = ldws;
-    a.r = (int)e.r;
-    a.vec = vec ? 1 : 0;
-    const int grid = (a.total + 7) / 8 * 8;
-    hipLaunchKernelGGL(kernel_for(l.prec, l.accumulate != 0, cfg), dim3(grid), dim3(dev::NT), 0, e.stream, a);
-    HIP_OK(hipGetLastError());
+    int grid = 0;
+    if (!make_args(c, li, cfg, e, a, grid)) continue;
+    KernelFn fn = kernel_for(l, cfg);
+    if (d->profiling) {
+      hipEvent_t ev[2];
+      for (int q = 0; q < 2; ++q) {
+        if (d->ev_used >= d->events.size()) {
+          hipEvent_t x;
+          HIP_OK(hipEventCreate(&x));
+          d->events.push_back(x);
+        }
+        ev[q] = d->events[d->ev_used++];
+      }
+      HIP_OK(hipEventRecord(ev[0], e.stream));
+      hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::NT), 0, e.stream, a);
+      HIP_OK(hipGetLastError());
+      HIP_OK(hipEventRecord(ev[1], e.stream));
+      d->pending.push_back({li, ev[0], ev[1]});
+    } else {
+      hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::NT), 0, e.stream, a);
+      HIP_OK(hipGetLastError());
+    }
   }
 }
 
@@ -478,7 +307,7 @@ void device_evaluate(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
   HIP_OK(hipGetDevice(&cur));
   if (c.dev->device != cur) fail(GOFMM_EINVAL, "current device differs from the compression's device");
   if (r > INT32_MAX / 2) fail(GOFMM_ELIMIT, "r too large");
-  launch_all(c, EvalArgs{r, W, ldw, U, ldu, (hipStream_t)stream}, -1);
+  launch_all(c, EvalArgs{r, W, ldw, U, ldu, (hipStream_t)stream});
 }
 
 // Time every configuration of every launch for this r and keep the fastest.
@@ -489,36 +318,21 @@ void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
-  DeviceState* d = c.dev;
-  const i64 ldws = ws_cols_for(r);
-  const bool vec = ((uintptr_t)W % 16 == 0) && ((uintptr_t)U % 16 == 0) && ldw % 4 == 0 && ldu % 4 == 0;
+  const EvalArgs e{r, W, ldw, U, ldu, st};
+  const bool prof = c.dev->profiling;
+  c.dev->profiling = false;
   for (int li = 0; li < (int)c.plan.launches.size(); ++li) {
-    const LaunchDesc& l = c.plan.launches[li];
     float best = 1e30f;
     int bc = choose_cfg(c, li, r);
     for (int q = 0; q < kNumCfg; ++q) {
-      const Cfg& g = kCfgs[q];
-      auto tl = tiles_for(c, li, g.bm);
-      if (tl.second == 0) continue;
       dev::KArgs a;
-      a.tasks = d->tasks;
-      a.tiles = tl.first;
-      a.ntn = (int)((r + g.bn - 1) / g.bn);
-      a.total = tl.second * a.ntn;
-      a.A = l.prec == PREC_F32 ? (const void*)d->a_f32 : l.prec == PREC_BF16 ? (const void*)d->a_b16 : (const void*)d->a_x3;
-      a.plane = d->x3_plane;
-      a.rows = d->rows;
-      a.W = W;
-      a.ldw = ldw;
-      a.U = U;
-      a.ldu = ldu;
-      a.WS = d->ws;
-      a.ldws = ldws;
-      a.r = (int)r;
-      a.vec = vec ? 1 : 0;
-      const int grid = (a.total + 7) / 8 * 8;
-      // accumulate-mode launches would change U; time them in overwrite mode
-      KernelFn fn = kernel_for(l.prec, false, q);
+      int grid = 0;
+      if (!make_args(c, li, q, e, a, grid)) continue;
+      // accumulating launches would change their output; time them overwriting
+      LaunchDesc lo = c.plan.launches[li];
+      if (lo.kind == 6) lo.kind = 1;
+      lo.accumulate = 0;
+      KernelFn fn = kernel_for(lo, q);
       hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::NT), 0, st, a);
       HIP_OK(hipEventRecord(e0, st));
       for (int t = 0; t < reps; ++t) hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::NT), 0, st, a);
@@ -527,13 +341,37 @@ void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
       float ms = 0.f;
       HIP_OK(hipEventElapsedTime(&ms, e0, e1));
       if (ms < best) { best = ms; bc = q; }
+      if (std::getenv("GOFMM_TUNE_LOG"))
+        std::fprintf(stderr, "tune %s r=%lld cfg %dx%d: %.4f ms\n", c.plan.launches[li].name.c_str(),
+                     (long long)r, kCfgs[q].bm, kCfgs[q].bn, ms / reps);
     }
-    d->tuned[(long long)li * (1ll << 32) + r] = bc;
+    c.dev->tuned[{li, r}] = bc;
   }
+  c.dev->profiling = prof;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   // the timing runs overwrote intermediate rows: recompute a clean result
   device_evaluate(c, r, W, ldw, U, ldu, stream);
+}
+
+void device_profile(Compression& c, int on) {
+  if (!c.dev) device_prepare(c, 1);
+  c.dev->profiling = on != 0;
+}
+
+// Sum of recorded launch times (ms) and record counts per launch; clears the records.
+void device_profile_read(Compression& c, int n, float* total_ms, int* calls) {
+  for (int i = 0; i < n; ++i) { total_ms[i] = 0.f; calls[i] = 0; }
+  if (!c.dev) return;
+  DeviceState* d = c.dev;
+  for (auto& r : d->pending) {
+    HIP_OK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+    if (r.launch < n) { total_ms[r.launch] += ms; calls[r.launch] += 1; }
+  }
+  d->pending.clear();
+  d->ev_used = 0;
 }
 
 i64 device_footprint(const Compression& c, i64 r_max) {
@@ -541,16 +379,13 @@ i64 device_footprint(const Compression& c, i64 r_max) {
   i64 b = (i64)(pl.a_f32.size() * 4 + pl.a_b16.size() * 2 + (pl.a_x3hi.size() + pl.a_x3lo.size()) * 2 +
                 pl.tasks.size() * sizeof(TaskDesc) + pl.rows.size() * 4);
   b += std::max<i64>(1, pl.ws_rows) * ws_cols_for(r_max) * 4;
-  // tile lists: at most one entry per 32 rows of every task, per configuration height
+  // work-item lists: one entry per 32 rows x 32 columns of every task, plus XCD padding
   i64 entries = 0;
   for (const auto& t : pl.tasks) entries += (t.m + 31) / 32;
-  b += entries * 8 * 3;
+  b += (entries * ((r_max + 31) / 32) + (i64)pl.launches.size() * kXcds) * 8;
   return b;
 }
 
-}  // namespace gofmm
-
-namespace gofmm {
 // Independent products, one after another on the stream (the persistent
 // single-launch form replaces this).
 void device_evaluate_batched(int k, Compression* const* c, const i64* r, const float* const* W,
@@ -558,4 +393,5 @@ void device_evaluate_batched(int k, Compression* const* c, const i64* r, const f
   for (int i = 0; i < k; ++i)
     if (r[i] > 0) device_evaluate(*c[i], r[i], W[i], ldw[i], U[i], ldu[i], stream);
 }
+
 }  // namespace gofmm

@@ -80,9 +80,11 @@ struct LaunchDesc {
   int prec;          // Prec of A for every task in the range
   int accumulate;    // 1: out += A B ; 0: out = A B
   i32 t_begin, t_end;
-  int kind;          // 0 n2s-leaf, 1 n2s-level, 2 s2s(+s2n)-level, 3 leaf-out, 4 s2n-leaf, 5 l2l
+  int kind;          // 0 n2s-leaf, 1 n2s-level, 2 s2s, 3 leaf-out, 4 s2n-leaf, 5 l2l, 6 s2n-level
   int level;
   std::string name;
+  double flops = 0;   // per right-hand side: sum of 2 m k over the tasks
+  i64 bytes = 0;      // operator bytes the launch reads
 };
 
 struct HostPlan {

@@ -1,0 +1,8 @@
+// Instantiates the gather-GEMM kernels for one operator precision.
+#include "kernels.hpp"
+
+namespace gofmm {
+namespace dev {
+void kernels_bf16(KernelFn* table) { fill_table<PREC_BF16>(table); }
+}  // namespace dev
+}  // namespace gofmm

@@ -1,0 +1,341 @@
+// Device code of the gather-GEMM evaluator (included by one translation unit
+// per precision, which instantiates the kernels).
+//
+// Every step of Alg. "Evaluate" (Sec. 2.2) is a list of gather-GEMM tasks
+// (see pack.cpp); one kernel template runs a list level by level:
+//
+//   out[m x r] (=|+=) A[m x k] B[k x r]
+//
+// A is a packed operator block (P, P^T, coupling K(b~, a~) or near K(b, a)),
+// B's rows are gathered by row code from the caller's W or from the skeleton
+// workspace, and out's rows are scattered the same way (the permutation is
+// folded into the codes).  Work item = one BM x BN output tile.  The k loop
+// stages a BM x 32 slab of A and a 32 x BN slab of B through LDS (B is
+// transposed on the way in so both operands are read k-contiguous), with the
+// next slab's global loads in flight while the matrix cores work on the
+// current one.  Matrix-core instructions (64-wide waves, 4 waves per block):
+//
+//   FP32    v_mfma_f32_32x32x2_f32   (A, B in FP32)
+//   BF16    v_mfma_f32_32x32x16_bf16 (A stored BF16, B rounded to BF16)
+//   BF16X3  three v_mfma_f32_32x32x16_bf16 per step on split operands,
+//           a_hi b_hi + a_hi b_lo + a_lo b_hi, with x = hi + lo, hi = bf16(x),
+//           lo = bf16(x - hi): about 16 significant bits per operand.
+//
+// Accumulation is FP32 in the matrix-core accumulators.  Each block reads its
+// work item (task, row tile, column tile) from a host-built list; the host
+// orders the list so that the longest tiles start first and the column tiles
+// of one A block run on the same XCD (sharing its L2).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace gofmm {
+// ------------------------------------------------------------------ device code
+namespace dev {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 32;
+constexpr int NT = 256;
+
+struct KArgs {
+  const TaskDesc* tasks;
+  const int2* items;    // per block: (task, m-tile << 16 | n-tile), task < 0 = idle
+  const void* A;
+  long long plane;      // offset of the lo plane (split BF16)
+  const int* rows;
+  const float* W;
+  long long ldw;
+  float* U;
+  long long ldu;
+  float* WS;
+  long long ldws;
+  int r;
+  int vec;              // rows of W, U, WS are 16-byte aligned
+};
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned int u = __builtin_bit_cast(unsigned int, f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short h) {
+  return __builtin_bit_cast(float, (unsigned int)h << 16);
+}
+
+template <int PREC, int BM, int BN, int WM, int WN, bool ACC>
+__device__ __forceinline__ void gemm_tiles(const KArgs& a) {
+  constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 32, TN = WTN / 32;
+  static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "tile shape");
+  constexpr bool F32 = PREC == PREC_F32;
+  constexpr bool X3 = PREC == PREC_BF16X3;
+  constexpr int NPL = X3 ? 2 : 1;                    // planes per operand
+  constexpr int LDK = F32 ? BK + 4 : BK + 8;         // LDS row stride (elements)
+  using E = typename std::conditional<F32, float, unsigned short>::type;
+  __shared__ __attribute__((aligned(16))) E sA[NPL * BM * LDK];
+  __shared__ __attribute__((aligned(16))) E sB[NPL * BN * LDK];
+  __shared__ int sOut[BM];
+
+  const int2 it = a.items[blockIdx.x];
+  if (it.x < 0) return;
+  const TaskDesc td = a.tasks[it.x];
+  const int m0 = (it.y >> 16) * BM;
+  const int n0 = (it.y & 0xffff) * BN;
+  const int tid = threadIdx.x;
+  const int* codes = a.rows + td.idx_off;
+  for (int i = tid; i < BM; i += NT) sOut[i] = (m0 + i < td.m) ? codes[td.lda + m0 + i] : ROW_ZERO;
+
+  constexpr int EPU = F32 ? 4 : 8;                   // A elements per 16-byte unit
+  constexpr int AU = BM * BK / EPU, AUT = (AU + NT - 1) / NT;
+  // B is loaded in sub-blocks of KS rows x 4 columns and transposed in
+  // registers, so that LDS receives k-contiguous 16-byte vectors per column.
+  constexpr int KS = 4;
+  constexpr int BSUB = (BK / KS) * (BN / 4), BST = (BSUB + NT - 1) / NT;
+  uint4 ra[NPL][AUT];
+  f32x4 rb[BST][KS];
+  const E* Ab = reinterpret_cast<const E*>(a.A);
+  // Row codes of B are fetched one slab ahead of the B rows they address, so
+  // that the address of a B load never waits on a code load.
+  int nc[BST][KS];
+  auto cload = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < BST; ++t) {
+      const int sub = tid + t * NT;
+      const int kq = sub / (BN / 4);
+#pragma unroll
+      for (int e = 0; e < KS; ++e)
+        nc[t][e] = (sub < BSUB && k0 < td.lda) ? codes[k0 + kq * KS + e] : ROW_ZERO;
+    }
+  };
+
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < AUT; ++t) {
+      const int u = tid + t * NT;
+      if (u < AU) {
+        const int row = u / (BK / EPU), c = u % (BK / EPU);
+        if (m0 + row < td.m) {
+          const long long off = td.a_off + (long long)(m0 + row) * td.lda + k0 + c * EPU;
+          ra[0][t] = *reinterpret_cast<const uint4*>(Ab + off);
+          if constexpr (X3) ra[NPL - 1][t] = *reinterpret_cast<const uint4*>(Ab + a.plane + off);
+        } else {
+#pragma unroll
+          for (int p = 0; p < NPL; ++p) ra[p][t] = make_uint4(0, 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < BST; ++t) {
+      const int sub = tid + t * NT;
+      if (sub < BSUB) {
+        const int cq = sub % (BN / 4), kq = sub / (BN / 4);
+        const int col = n0 + 4 * cq;
+#pragma unroll
+        for (int e = 0; e < KS; ++e) {
+          const int code = nc[t][e];
+          f32x4 v = {0.f, 0.f, 0.f, 0.f};
+          if (code != ROW_ZERO) {
+            const float* p = code >= 0 ? a.W + (long long)code * a.ldw
+                                       : a.WS + (long long)(-(code + 1)) * a.ldws;
+            if (a.vec && col + 3 < a.r) {
+              v = *reinterpret_cast<const f32x4*>(p + col);
+            } else {
+              if (col < a.r) v[0] = p[col];
+              if (col + 1 < a.r) v[1] = p[col + 1];
+              if (col + 2 < a.r) v[2] = p[col + 2];
+              if (col + 3 < a.r) v[3] = p[col + 3];
+            }
+          }
+          rb[t][e] = v;
+        }
+      }
+    }
+  };
+
+  auto lstore = [&]() {
+#pragma unroll
+    for (int t = 0; t < AUT; ++t) {
+      const int u = tid + t * NT;
+      if (u < AU) {
+        const int row = u / (BK / EPU), c = u % (BK / EPU);
+#pragma unroll
+        for (int p = 0; p < NPL; ++p)
+          *reinterpret_cast<uint4*>(&sA[p * BM * LDK + row * LDK + c * EPU]) = ra[p][t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < BST; ++t) {
+      const int sub = tid + t * NT;
+      if (sub < BSUB) {
+        const int cq = sub % (BN / 4), kq = sub / (BN / 4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int idx = (4 * cq + j) * LDK + kq * KS;
+          if constexpr (F32) {
+            f32x4 v = {rb[t][0][j], rb[t][1][j], rb[t][2][j], rb[t][3][j]};
+            *reinterpret_cast<f32x4*>(&sB[idx]) = v;
+          } else {
+            u16x4 hi, lo;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              hi[e] = bf16_rne(rb[t][e][j]);
+              if constexpr (X3) lo[e] = bf16_rne(rb[t][e][j] - bf16_val(hi[e]));
+            }
+            *reinterpret_cast<u16x4*>(&sB[idx]) = hi;
+            if constexpr (X3) *reinterpret_cast<u16x4*>(&sB[BN * LDK + idx]) = lo;
+          }
+        }
+      }
+    }
+  };
+
+  const int lane = tid & 63, li = lane & 31, lh = lane >> 5;
+  const int wid = tid >> 6, wr = wid / WN, wc = wid % WN;
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  auto compute = [&]() {
+    if constexpr (F32) {
+      // lane (li, lh) feeds k = lh * 16 + 4u + q: the two halves of the wave
+      // cover k 0..15 and 16..31 of the slab, matching A and B.
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        f32x4 av[TM], bv[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          av[i] = *reinterpret_cast<const f32x4*>(&sA[(wr * WTM + i * 32 + li) * LDK + lh * 16 + 4 * u]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          bv[j] = *reinterpret_cast<const f32x4*>(&sB[(wc * WTN + j * 32 + li) * LDK + lh * 16 + 4 * u]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][q], bv[j][q], acc[i][j], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        bf16x8 ah[TM], bh[TN], al[TM], bl[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const int o = (wr * WTM + i * 32 + li) * LDK + 16 * s + 8 * lh;
+          ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sA[o]));
+          if constexpr (X3) al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sA[BM * LDK + o]));
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int o = (wc * WTN + j * 32 + li) * LDK + 16 * s + 8 * lh;
+          bh[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sB[o]));
+          if constexpr (X3) bl[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sB[BN * LDK + o]));
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            if constexpr (X3) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            }
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+  };
+
+  const int nk = td.lda / BK;
+  if (nk > 0) {
+    cload(0);
+    gload(0);
+    cload(BK);
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    lstore();
+    __syncthreads();
+    if (kt + 1 < nk) {
+      gload((kt + 1) * BK);
+      cload((kt + 2) * BK);
+    }
+    compute();
+  }
+  __syncthreads();
+
+  // epilogue: accumulator (i, j, v) of lane (li, lh) is row 8(v/4) + 4 lh + v%4,
+  // column li of the 32 x 32 block
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = wr * WTM + i * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
+      if (m0 + row >= td.m) continue;
+      const int code = sOut[row];
+      float* p = code >= 0 ? a.U + (long long)code * a.ldu : a.WS + (long long)(-(code + 1)) * a.ldws;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = n0 + wc * WTN + j * 32 + li;
+        if (col < a.r) {
+          if constexpr (ACC) p[col] += acc[i][j][v];
+          else p[col] = acc[i][j][v];
+        }
+      }
+    }
+}
+
+// Entry points with the same body, so that profiles separate the upward pass,
+// the far field, the downward pass and the leaf output.
+template <int PREC, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(NT) void n2s_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false>(a); }
+template <int PREC, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(NT) void s2s_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false>(a); }
+template <int PREC, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(NT) void s2n_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, true>(a); }
+template <int PREC, int BM, int BN, int WM, int WN, bool ACC>
+__global__ __launch_bounds__(NT) void leaf_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, ACC>(a); }
+
+typedef void (*KernelFn)(KArgs);
+constexpr int kNumCfg = 6;
+constexpr int kNumFamily = 5;   // n2s, s2s, s2n (accumulate), leaf, leaf accumulating
+struct Cfg { int bm, bn; };
+constexpr Cfg kCfgs[kNumCfg] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}, {128, 32}, {32, 128}};
+
+template <int PREC, int BM, int BN, int WM, int WN>
+void fill_family(KernelFn* row) {
+  row[0] = n2s_tiles<PREC, BM, BN, WM, WN>;
+  row[1] = s2s_tiles<PREC, BM, BN, WM, WN>;
+  row[2] = s2n_tiles<PREC, BM, BN, WM, WN>;
+  row[3] = leaf_tiles<PREC, BM, BN, WM, WN, false>;
+  row[4] = leaf_tiles<PREC, BM, BN, WM, WN, true>;
+}
+
+// table[cfg * kNumFamily + family]
+template <int PREC>
+void fill_table(KernelFn* table) {
+  fill_family<PREC, 128, 128, 2, 2>(table + 0 * kNumFamily);
+  fill_family<PREC, 128, 64, 2, 2>(table + 1 * kNumFamily);
+  fill_family<PREC, 64, 128, 2, 2>(table + 2 * kNumFamily);
+  fill_family<PREC, 64, 64, 2, 2>(table + 3 * kNumFamily);
+  fill_family<PREC, 128, 32, 4, 1>(table + 4 * kNumFamily);
+  fill_family<PREC, 32, 128, 1, 4>(table + 5 * kNumFamily);
+}
+
+void kernels_f32(KernelFn* table);
+void kernels_bf16(KernelFn* table);
+void kernels_x3(KernelFn* table);
+
+}  // namespace dev
+}  // namespace gofmm

@@ -8,9 +8,10 @@
 //
 //   n2s-leaf        w~_b = P_b W[perm(b)]                          (N2S, leaves)
 //   n2s-level l     w~_a = P_a [w~_l; w~_r]           for l = D-1 .. 1 (N2S)
-//   s2s-level l     u~_b = [K(b~, a~1) ... | (P_p^T)_b] [w~_a1; ...; u~_p]
-//                   for l = 1 .. D: S2S of b fused with the S2N push from b's
-//                   parent p; each child has one parent, so no atomics
+//   s2s             u~_b = [K(b~, a~1) | K(b~, a~2) ...] [w~_a1; w~_a2; ...]
+//                   for every non-root node in one launch
+//   s2n-level l     u~_c += (P_p^T)_c u~_p for the nodes c of level l = 2 .. D,
+//                   p the parent of c (each task owns its child's rows)
 //   leaf            U[perm(b)] = [P_b^T | K(b, a1) ...] [u~_b; W[perm(a1)]; ...]
 //                   (S2N at the leaf fused with L2L; U written once)
 //
@@ -120,25 +121,35 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
       }
       end_launch();
     }
-    // S2S fused with the S2N push from the parent, top down
-    for (int lev = 1; lev <= D; ++lev) {
-      begin_launch(pst, 0, 2, lev, "s2s_l" + std::to_string(lev));
+    // S2S for every non-root node in one launch (any order once w~ is ready)
+    begin_launch(pst, 0, 2, 0, "s2s");
+    for (i64 h = 1; h < nn; ++h) {
+      Draft d;
+      d.prec = pst;
+      d.m = c.rank(h);
+      for (i64 a : c.far[h]) {
+        d.parts.push_back({2, 0, 0, 0, c.skel[h], c.skel[a], c.rank(a)});
+        for (i64 j = 0; j < c.rank(a); ++j) d.brow.push_back(wrow(a, j));
+      }
+      for (i64 j = 0; j < d.m; ++j) d.orow.push_back(urow(h, j));
+      drafts.push_back(std::move(d));
+    }
+    end_launch();
+    // S2N down the levels, pull form: u~_c += (P_p^T)_c u~_p for every child c
+    // of an internal node p, children at level l = 2 .. D (no atomics: each
+    // task owns the rows of its child)
+    for (int lev = 2; lev <= D; ++lev) {
+      begin_launch(pst, 1, 6, lev, "s2n_l" + std::to_string(lev));
       for (i64 h = (i64(1) << lev) - 1; h < (i64(2) << lev) - 1; ++h) {
+        const i64 p = (h - 1) / 2;
+        const i64 sl = c.rank(2 * p + 1);
+        const bool left = (h == 2 * p + 1);
+        const i64 c0 = left ? 0 : sl, c1 = left ? sl : sl + c.rank(2 * p + 2);
         Draft d;
         d.prec = pst;
         d.m = c.rank(h);
-        for (i64 a : c.far[h]) {
-          d.parts.push_back({2, 0, 0, 0, c.skel[h], c.skel[a], c.rank(a)});
-          for (i64 j = 0; j < c.rank(a); ++j) d.brow.push_back(wrow(a, j));
-        }
-        if (lev >= 2) {
-          const i64 p = (h - 1) / 2;
-          const i64 sl = c.rank(2 * p + 1);
-          const bool left = (h == 2 * p + 1);
-          const i64 c0 = left ? 0 : sl, c1 = left ? sl : sl + c.rank(2 * p + 2);
-          d.parts.push_back({1, p, c0, c1, {}, {}, c.rank(p)});
-          for (i64 j = 0; j < c.rank(p); ++j) d.brow.push_back(urow(p, j));
-        }
+        d.parts.push_back({1, p, c0, c1, {}, {}, c.rank(p)});
+        for (i64 j = 0; j < c.rank(p); ++j) d.brow.push_back(urow(p, j));
         for (i64 j = 0; j < d.m; ++j) d.orow.push_back(urow(h, j));
         drafts.push_back(std::move(d));
       }
@@ -230,10 +241,12 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
 
   // flop and byte accounting per right-hand side (Table 2)
   for (size_t li = 0; li < pl.launches.size(); ++li) {
-    const LaunchDesc& l = pl.launches[li];
+    LaunchDesc& l = pl.launches[li];
     for (i32 t = l.t_begin; t < l.t_end; ++t) {
       const Draft& d = drafts[t];
       for (const Part& p : d.parts) {
+        l.flops += 2.0 * (double)d.m * (double)p.width;
+        l.bytes += d.m * p.width * elem_bytes(d.prec);
         int ph;
         if (p.type == 0) ph = PH_N2S;
         else if (p.type == 1) ph = PH_S2N;

@@ -63,6 +63,11 @@ SIGNATURES = [
     ("gofmm_evaluate_batched", C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_void_p]),
+    ("gofmm_launch_count", C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    ("gofmm_launch_info", C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_int64)]),
+    ("gofmm_profile", C.c_int, [C.c_void_p, C.c_int32]),
+    ("gofmm_profile_read", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     ("gofmm_footprint", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
     ("gofmm_stats", C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     ("gofmm_free", None, [C.c_void_p]),
@@ -193,6 +198,30 @@ class Compression:
         b = C.c_int64()
         _check(lib().gofmm_footprint(self.h, r_max, C.byref(b)))
         return int(b.value)
+
+    def launches(self):
+        """[(name, flops per rhs, operator bytes)] of the launches of one evaluate."""
+        n = C.c_int32()
+        _check(lib().gofmm_launch_count(self.h, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            buf = C.create_string_buffer(64)
+            f = C.c_double()
+            b = C.c_int64()
+            _check(lib().gofmm_launch_info(self.h, i, buf, 64, C.byref(f), C.byref(b)))
+            out.append((buf.value.decode(), f.value, b.value))
+        return out
+
+    def profile(self, enable: bool):
+        _check(lib().gofmm_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(total ms, record count) per launch since profiling was enabled."""
+        n = len(self.launches())
+        ms = (C.c_float * n)()
+        cnt = (C.c_int32 * n)()
+        _check(lib().gofmm_profile_read(self.h, n, ms, cnt))
+        return list(ms), list(cnt)
 
     def evaluate(self, W, U=None, stream=None):
         """U = K~ W for a CUDA float32 tensor W of shape (n, r)."""
