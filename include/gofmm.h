@@ -166,6 +166,30 @@ int gofmm_evaluate_batched(int32_t k, gofmm_compression* const* c, const int64_t
                            float* const* U, const int64_t* ldu, void* hip_stream);
 
 /*
+ * Time the batched launch of these k products with every tile configuration
+ * and keep the fastest for this set of compressions and r values (later
+ * batched calls with the same set reuse it).  Leaves U_i = K~_i W_i.
+ * Synchronizes the stream.
+ */
+int gofmm_autotune_batched(int32_t k, gofmm_compression* const* c, const int64_t* r,
+                           const float* const* W, const int64_t* ldw,
+                           float* const* U, const int64_t* ldu, void* hip_stream);
+
+/*
+ * Wait for the device and report the last batched launch on this process:
+ * *error = 1 if a block gave up a dependency wait (see
+ * gofmm_batched_spin_limit), else 0.  The flag is cleared on the next launch.
+ */
+int gofmm_batched_status(int32_t* error);
+
+/*
+ * Bound on the polls of one dependency wait in batched launches (default
+ * 2^21, a few seconds).  A wait that reaches it sets the error flag and its
+ * tile is skipped, so a launch always ends.  <= 0 restores the default.
+ */
+int gofmm_batched_spin_limit(int64_t polls);
+
+/*
  * Launches of one evaluate, in order.  For launch i: its name (e.g. "n2s_leaf",
  * "s2s_l3", "leaf"), the Table 2 flops it performs per right-hand side, and
  * the operator bytes it reads.  name receives at most name_len bytes

@@ -18,6 +18,10 @@ void device_evaluate_batched(int k, Compression* const* c, const i64* r, const f
                              const i64* ldw, float* const* U, const i64* ldu, void* stream);
 i64 device_footprint(const Compression& c, i64 r_max);
 void device_profile(Compression& c, int on);
+void device_autotune_batched(int k, Compression* const* c, const i64* r, const float* const* W,
+                             const i64* ldw, float* const* U, const i64* ldu, void* stream, int reps);
+int device_batched_status();
+void device_set_spin_limit(long long v);
 void device_profile_read(Compression& c, int n, float* total_ms, int* calls);
 
 }  // namespace gofmm
@@ -160,22 +164,58 @@ extern "C" int gofmm_autotune(gofmm_compression* c, int64_t r, const float* W, i
   });
 }
 
+static std::vector<Compression*> batch_args(int32_t k, gofmm_compression* const* c, const int64_t* r,
+                                            const float* const* W, const int64_t* ldw, float* const* U,
+                                            const int64_t* ldu) {
+  if (!c || !r || !W || !ldw || !U || !ldu) fail(GOFMM_EINVAL, "NULL argument");
+  std::vector<Compression*> cs(k);
+  for (int i = 0; i < k; ++i) {
+    check_eval(c[i], r[i], W[i], ldw[i], U[i], ldu[i]);
+    if (r[i] < 1) fail(GOFMM_EINVAL, "every instance of a batch needs r >= 1");
+    for (int j = 0; j < i; ++j) {
+      if (c[j] == c[i]) fail(GOFMM_EINVAL, "a compression appears twice in one batch");
+      const char* a0 = (const char*)U[i];
+      const char* a1 = a0 + ((c[i]->c.n - 1) * ldu[i] + r[i]) * 4;
+      const char* b0 = (const char*)U[j];
+      const char* b1 = b0 + ((c[j]->c.n - 1) * ldu[j] + r[j]) * 4;
+      if (a0 < b1 && b0 < a1) fail(GOFMM_EINVAL, "outputs of two instances overlap");
+    }
+    cs[i] = &c[i]->c;
+  }
+  return cs;
+}
+
 extern "C" int gofmm_evaluate_batched(int32_t k, gofmm_compression* const* c, const int64_t* r,
                                       const float* const* W, const int64_t* ldw, float* const* U,
                                       const int64_t* ldu, void* hip_stream) {
   return guarded([&] {
     if (k < 0) fail(GOFMM_EINVAL, "k must be >= 0");
     if (k == 0) return;
-    if (!c || !r || !W || !ldw || !U || !ldu) fail(GOFMM_EINVAL, "NULL argument");
-    std::vector<Compression*> cs(k);
-    for (int i = 0; i < k; ++i) {
-      check_eval(c[i], r[i], W[i], ldw[i], U[i], ldu[i]);
-      for (int j = 0; j < i; ++j)
-        if (c[j] == c[i]) fail(GOFMM_EINVAL, "a compression appears twice in one batch");
-      cs[i] = &c[i]->c;
-    }
+    auto cs = batch_args(k, c, r, W, ldw, U, ldu);
     device_evaluate_batched(k, cs.data(), r, W, ldw, U, ldu, hip_stream);
   });
+}
+
+extern "C" int gofmm_autotune_batched(int32_t k, gofmm_compression* const* c, const int64_t* r,
+                                      const float* const* W, const int64_t* ldw, float* const* U,
+                                      const int64_t* ldu, void* hip_stream) {
+  return guarded([&] {
+    if (k < 0) fail(GOFMM_EINVAL, "k must be >= 0");
+    if (k == 0) return;
+    auto cs = batch_args(k, c, r, W, ldw, U, ldu);
+    device_autotune_batched(k, cs.data(), r, W, ldw, U, ldu, hip_stream, 3);
+  });
+}
+
+extern "C" int gofmm_batched_status(int32_t* error) {
+  return guarded([&] {
+    if (!error) fail(GOFMM_EINVAL, "NULL argument");
+    *error = device_batched_status();
+  });
+}
+
+extern "C" int gofmm_batched_spin_limit(int64_t polls) {
+  return guarded([&] { device_set_spin_limit(polls); });
 }
 
 extern "C" int gofmm_launch_count(const gofmm_compression* c, int32_t* count) {

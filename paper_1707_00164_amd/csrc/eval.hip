@@ -28,6 +28,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <memory>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -52,16 +53,22 @@ static int family_of(const LaunchDesc& l) {
   return l.accumulate ? 4 : 3;
 }
 
-static KernelFn kernel_for(const LaunchDesc& l, int cfg) {
-  static KernelFn tables[3][kNumCfg * kNumFamily];
-  static bool init = false;
-  if (!init) {
-    dev::kernels_f32(tables[PREC_F32]);
-    dev::kernels_bf16(tables[PREC_BF16]);
-    dev::kernels_x3(tables[PREC_BF16X3]);
-    init = true;
+struct Tables {
+  KernelFn k[3][kNumCfg * kNumFamily];
+  dev::BatchedFn b[3][kNumCfg];
+  Tables() {
+    dev::kernels_f32(k[PREC_F32], b[PREC_F32]);
+    dev::kernels_bf16(k[PREC_BF16], b[PREC_BF16]);
+    dev::kernels_x3(k[PREC_BF16X3], b[PREC_BF16X3]);
   }
-  return tables[l.prec][cfg * kNumFamily + family_of(l)];
+};
+static const Tables& tables() {
+  static Tables t;
+  return t;
+}
+
+static KernelFn kernel_for(const LaunchDesc& l, int cfg) {
+  return tables().k[l.prec][cfg * kNumFamily + family_of(l)];
 }
 
 // ------------------------------------------------------------------ device state
@@ -386,12 +393,260 @@ i64 device_footprint(const Compression& c, i64 r_max) {
   return b;
 }
 
-// Independent products, one after another on the stream (the persistent
-// single-launch form replaces this).
+// ------------------------------------------------------------------ batched launch
+struct BatchPlan;
+static BatchPlan*& last_batch() {
+  static BatchPlan* p = nullptr;
+  return p;
+}
+static long long& spin_limit_ref() {
+  static long long v = 1ll << 21;
+  return v;
+}
+static long long batch_spin_limit() { return spin_limit_ref(); }
+void device_set_spin_limit(long long v) { spin_limit_ref() = v > 0 ? v : (1ll << 21); }
+
+struct BatchPlan {
+  std::vector<uint64_t> key;     // compression ids and r values, then the configuration
+  int prec = 0, cfg = 0;
+  dev::BItem* items = nullptr;
+  int n_items = 0;
+  int* stage_tab = nullptr;      // prev, need, acc (3 x n_stages)
+  int n_stages = 0;
+  int* counters = nullptr;       // done[n_stages], head, error
+  dev::BInst* inst = nullptr;
+  int k = 0;
+  int grid = 0;
+  ~BatchPlan() {
+    (void)hipFree(items);
+    (void)hipFree(stage_tab);
+    (void)hipFree(counters);
+    (void)hipFree(inst);
+  }
+};
+
+static std::vector<std::unique_ptr<BatchPlan>>& batch_cache() {
+  static std::vector<std::unique_ptr<BatchPlan>> c;   // most recent last
+  return c;
+}
+static std::map<std::vector<uint64_t>, int>& batch_tuned() {
+  static std::map<std::vector<uint64_t>, int> t;
+  return t;
+}
+
+static std::vector<uint64_t> batch_key(int k, Compression* const* c, const i64* r) {
+  std::vector<uint64_t> key;
+  for (int i = 0; i < k; ++i) {
+    key.push_back(c[i]->uid);
+    key.push_back((uint64_t)r[i]);
+  }
+  return key;
+}
+
+static int batch_prec(int k, Compression* const* c) {
+  int prec = -1;
+  for (int i = 0; i < k; ++i)
+    for (const LaunchDesc& l : c[i]->plan.launches) {
+      if (prec < 0) prec = l.prec;
+      else if (prec != l.prec)
+        fail(GOFMM_EINVAL, "a batched launch needs one storage precision for every step of every compression");
+    }
+  return prec < 0 ? PREC_F32 : prec;
+}
+
+// Stage-major queue: stage j of every instance precedes stage j + 1 of any;
+// within a stage position, tiles are ordered longest-k first.
+static BatchPlan* batch_plan(int k, Compression* const* c, const i64* r, int cfg) {
+  std::vector<uint64_t> key = batch_key(k, c, r);
+  key.push_back((uint64_t)cfg);
+  auto& cache = batch_cache();
+  for (size_t i = 0; i < cache.size(); ++i)
+    if (cache[i]->key == key) {
+      std::unique_ptr<BatchPlan> p = std::move(cache[i]);
+      cache.erase(cache.begin() + i);
+      cache.push_back(std::move(p));
+      return cache.back().get();
+    }
+  std::unique_ptr<BatchPlan> bp(new BatchPlan);
+  bp->key = key;
+  bp->prec = batch_prec(k, c);
+  bp->cfg = cfg;
+  bp->k = k;
+  const Cfg& g = kCfgs[cfg];
+  std::vector<int> prev, need, acc;
+  std::vector<std::vector<int>> stage_of(k);   // stage id of instance i's j-th launch
+  size_t max_l = 0;
+  for (int i = 0; i < k; ++i) max_l = std::max(max_l, c[i]->plan.launches.size());
+  std::vector<dev::BItem> items;
+  for (size_t j = 0; j < max_l; ++j) {
+    struct T { dev::BItem it; i64 cost; };
+    std::vector<T> pos;
+    for (int i = 0; i < k; ++i) {
+      const HostPlan& pl = c[i]->plan;
+      if (j >= pl.launches.size()) continue;
+      const LaunchDesc& l = pl.launches[j];
+      const int sid = (int)prev.size();
+      const int ntn = (int)((r[i] + g.bn - 1) / g.bn);
+      int count = 0;
+      for (i32 t = l.t_begin; t < l.t_end; ++t)
+        for (int mt = 0; mt * g.bm < pl.tasks[t].m; ++mt)
+          for (int nt = 0; nt < ntn; ++nt) {
+            pos.push_back({{i, sid, t, (mt << 16) | nt}, (i64)std::max(pl.tasks[t].lda, 32)});
+            ++count;
+          }
+      const int ps = j == 0 ? -1 : stage_of[i][j - 1];
+      prev.push_back(ps);
+      need.push_back(ps < 0 ? 0 : 0);
+      acc.push_back(l.accumulate);
+      stage_of[i].push_back(sid);
+      // remember the tile count of this stage for its successor's wait
+      need.back() = count;          // temporarily the stage's own count
+    }
+    std::stable_sort(pos.begin(), pos.end(), [](const T& x, const T& y) { return x.cost > y.cost; });
+    for (auto& t : pos) items.push_back(t.it);
+  }
+  // need[s] must be the tile count of prev[s]; convert from own counts
+  std::vector<int> own(need);
+  for (size_t s2 = 0; s2 < prev.size(); ++s2) need[s2] = prev[s2] < 0 ? 0 : own[prev[s2]];
+  bp->n_stages = (int)prev.size();
+  bp->n_items = (int)items.size();
+  std::vector<int> tab(prev);
+  tab.insert(tab.end(), need.begin(), need.end());
+  tab.insert(tab.end(), acc.begin(), acc.end());
+  if (!items.empty()) {
+    HIP_OK(hipMalloc((void**)&bp->items, items.size() * sizeof(dev::BItem)));
+    HIP_OK(hipMemcpy(bp->items, items.data(), items.size() * sizeof(dev::BItem), hipMemcpyHostToDevice));
+  }
+  HIP_OK(hipMalloc((void**)&bp->stage_tab, std::max<size_t>(1, tab.size()) * sizeof(int)));
+  if (!tab.empty()) HIP_OK(hipMemcpy(bp->stage_tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_OK(hipMalloc((void**)&bp->counters, (bp->n_stages + 2) * sizeof(int)));
+  HIP_OK(hipMalloc((void**)&bp->inst, k * sizeof(dev::BInst)));
+  dev::BatchedFn fn = tables().b[bp->prec][cfg];
+  int per_cu = 0, cus = 0, devid = 0;
+  HIP_OK(hipGetDevice(&devid));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, dev::NT, 0));
+  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
+  bp->grid = std::max(1, std::min(bp->n_items, std::max(1, per_cu) * std::max(1, cus)));
+  if (cache.size() >= 16) {
+    if (last_batch() == cache.front().get()) last_batch() = nullptr;
+    cache.erase(cache.begin());
+  }
+  cache.push_back(std::move(bp));
+  return cache.back().get();
+}
+
+static int batch_cfg_model(int k, Compression* const* c, const i64* r) {
+  double best = 1e300;
+  int bc = 0;
+  for (int q = 0; q < kNumCfg; ++q) {
+    const Cfg& g = kCfgs[q];
+    double cost = 0.0;
+    for (int i = 0; i < k; ++i) {
+      const double nt = (double)((r[i] + g.bn - 1) / g.bn);
+      for (const TaskDesc& t : c[i]->plan.tasks)
+        cost += (double)((t.m + g.bm - 1) / g.bm) * nt * (g.bm * g.bn * (double)std::max(t.lda, 32) + 32.0 * 128 * 128);
+    }
+    if (cost < best) { best = cost; bc = q; }
+  }
+  return bc;
+}
+
+static void batch_launch(BatchPlan* bp, int k, Compression* const* c, const i64* r, const float* const* W,
+                         const i64* ldw, float* const* U, const i64* ldu, hipStream_t st) {
+  std::vector<dev::BInst> in(k);
+  for (int i = 0; i < k; ++i) {
+    DeviceState* d = c[i]->dev;
+    const int prec = bp->prec;
+    in[i].tasks = d->tasks;
+    in[i].rows = d->rows;
+    in[i].A = prec == PREC_F32 ? (const void*)d->a_f32 : prec == PREC_BF16 ? (const void*)d->a_b16 : (const void*)d->a_x3;
+    in[i].plane = d->x3_plane;
+    in[i].W = W[i];
+    in[i].ldw = ldw[i];
+    in[i].U = U[i];
+    in[i].ldu = ldu[i];
+    in[i].WS = d->ws;
+    in[i].ldws = ws_cols_for(r[i]);
+    in[i].r = (int)r[i];
+    in[i].vec = ((uintptr_t)W[i] % 16 == 0) && ((uintptr_t)U[i] % 16 == 0) && ldw[i] % 4 == 0 && ldu[i] % 4 == 0;
+  }
+  HIP_OK(hipMemcpyAsync(bp->inst, in.data(), k * sizeof(dev::BInst), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemsetAsync(bp->counters, 0, (bp->n_stages + 2) * sizeof(int), st));
+  if (bp->n_items == 0) return;
+  dev::BArgs a;
+  a.inst = bp->inst;
+  a.items = bp->items;
+  a.n_items = bp->n_items;
+  a.stage_prev = bp->stage_tab;
+  a.stage_need = bp->stage_tab + bp->n_stages;
+  a.stage_acc = bp->stage_tab + 2 * bp->n_stages;
+  a.done = bp->counters;
+  a.head = bp->counters + bp->n_stages;
+  a.error = bp->counters + bp->n_stages + 1;
+  a.spin_limit = batch_spin_limit();
+  hipLaunchKernelGGL(tables().b[bp->prec][bp->cfg], dim3(bp->grid), dim3(dev::NT), 0, st, a);
+  HIP_OK(hipGetLastError());
+  last_batch() = bp;
+}
+
+static void batch_prepare(int k, Compression* const* c, const i64* r) {
+  int cur;
+  HIP_OK(hipGetDevice(&cur));
+  for (int i = 0; i < k; ++i) {
+    if (r[i] < 1) fail(GOFMM_EINVAL, "every instance of a batch needs r >= 1");
+    if (!c[i]->dev || ws_cols_for(r[i]) > c[i]->dev->ws_cols) device_prepare(*c[i], r[i]);
+    if (c[i]->dev->device != cur) fail(GOFMM_EINVAL, "current device differs from a compression's device");
+  }
+}
+
+// All instances' steps in one persistent launch.
 void device_evaluate_batched(int k, Compression* const* c, const i64* r, const float* const* W,
                              const i64* ldw, float* const* U, const i64* ldu, void* stream) {
-  for (int i = 0; i < k; ++i)
-    if (r[i] > 0) device_evaluate(*c[i], r[i], W[i], ldw[i], U[i], ldu[i], stream);
+  batch_prepare(k, c, r);
+  auto it = batch_tuned().find(batch_key(k, c, r));
+  const int cfg = it != batch_tuned().end() ? it->second : batch_cfg_model(k, c, r);
+  BatchPlan* bp = batch_plan(k, c, r, cfg);
+  batch_launch(bp, k, c, r, W, ldw, U, ldu, (hipStream_t)stream);
+}
+
+// Time the whole batched launch with every tile configuration; keep the fastest.
+void device_autotune_batched(int k, Compression* const* c, const i64* r, const float* const* W,
+                             const i64* ldw, float* const* U, const i64* ldu, void* stream, int reps) {
+  batch_prepare(k, c, r);
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bc = batch_cfg_model(k, c, r);
+  for (int q = 0; q < kNumCfg; ++q) {
+    BatchPlan* bp = batch_plan(k, c, r, q);
+    batch_launch(bp, k, c, r, W, ldw, U, ldu, st);
+    HIP_OK(hipEventRecord(e0, st));
+    for (int t = 0; t < reps; ++t) batch_launch(bp, k, c, r, W, ldw, U, ldu, st);
+    HIP_OK(hipEventRecord(e1, st));
+    HIP_OK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    if (std::getenv("GOFMM_TUNE_LOG"))
+      std::fprintf(stderr, "tune batched k=%d cfg %dx%d: %.4f ms\n", k, kCfgs[q].bm, kCfgs[q].bn, ms / reps);
+    if (ms < best) { best = ms; bc = q; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  batch_tuned()[batch_key(k, c, r)] = bc;
+  device_evaluate_batched(k, c, r, W, ldw, U, ldu, stream);
+}
+
+// Waits for the device, then reports and clears the error flag of the last
+// batched launch (1 if a dependency wait hit its spin limit).
+int device_batched_status() {
+  BatchPlan* bp = last_batch();
+  if (!bp) return 0;
+  HIP_OK(hipDeviceSynchronize());
+  int flag = 0;
+  HIP_OK(hipMemcpy(&flag, bp->counters + bp->n_stages + 1, sizeof(int), hipMemcpyDeviceToHost));
+  return flag;
 }
 
 }  // namespace gofmm

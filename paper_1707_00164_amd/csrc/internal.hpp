@@ -2,6 +2,7 @@
 // format and the device evaluator.  Not part of the public ABI.
 #pragma once
 
+#include <atomic>
 #include <climits>
 #include <cstdint>
 #include <cstring>
@@ -129,6 +130,11 @@ struct Compression {
   // device operator
   HostPlan plan;
   DeviceState* dev = nullptr;
+  uint64_t uid = next_uid();   // identity for caches keyed by compression
+  static uint64_t next_uid() {
+    static std::atomic<uint64_t> counter{0};
+    return ++counter;
+  }
 
   i64 nn() const { return n_nodes(depth); }
   i64 fl() const { return first_leaf(depth); }

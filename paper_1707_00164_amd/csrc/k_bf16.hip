@@ -3,6 +3,6 @@
 
 namespace gofmm {
 namespace dev {
-void kernels_bf16(KernelFn* table) { fill_table<PREC_BF16>(table); }
+void kernels_bf16(KernelFn* table, BatchedFn* batched) { fill_table<PREC_BF16>(table, batched); }
 }  // namespace dev
 }  // namespace gofmm

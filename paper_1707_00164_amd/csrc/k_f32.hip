@@ -3,6 +3,6 @@
 
 namespace gofmm {
 namespace dev {
-void kernels_f32(KernelFn* table) { fill_table<PREC_F32>(table); }
+void kernels_f32(KernelFn* table, BatchedFn* batched) { fill_table<PREC_F32>(table, batched); }
 }  // namespace dev
 }  // namespace gofmm

@@ -3,6 +3,6 @@
 
 namespace gofmm {
 namespace dev {
-void kernels_x3(KernelFn* table) { fill_table<PREC_BF16X3>(table); }
+void kernels_x3(KernelFn* table, BatchedFn* batched) { fill_table<PREC_BF16X3>(table, batched); }
 }  // namespace dev
 }  // namespace gofmm

@@ -70,24 +70,33 @@ __device__ __forceinline__ float bf16_val(unsigned short h) {
   return __builtin_bit_cast(float, (unsigned int)h << 16);
 }
 
+// LDS of one block: A and B slabs (two planes each for split BF16) and the
+// output row codes of the tile.
+template <int PREC, int BM, int BN>
+struct Smem {
+  static constexpr bool F32 = PREC == PREC_F32;
+  static constexpr int NPL = PREC == PREC_BF16X3 ? 2 : 1;
+  static constexpr int LDK = F32 ? BK + 4 : BK + 8;  // row stride (elements)
+  using E = typename std::conditional<F32, float, unsigned short>::type;
+  __attribute__((aligned(16))) E sA[NPL * BM * LDK];
+  __attribute__((aligned(16))) E sB[NPL * BN * LDK];
+  int sOut[BM];
+};
+
+// One BM x BN output tile of task td (rows m0.., columns n0..).
 template <int PREC, int BM, int BN, int WM, int WN, bool ACC>
-__device__ __forceinline__ void gemm_tiles(const KArgs& a) {
+__device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, int m0, int n0,
+                                          Smem<PREC, BM, BN>& sm) {
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 32, TN = WTN / 32;
   static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "tile shape");
   constexpr bool F32 = PREC == PREC_F32;
   constexpr bool X3 = PREC == PREC_BF16X3;
   constexpr int NPL = X3 ? 2 : 1;                    // planes per operand
-  constexpr int LDK = F32 ? BK + 4 : BK + 8;         // LDS row stride (elements)
-  using E = typename std::conditional<F32, float, unsigned short>::type;
-  __shared__ __attribute__((aligned(16))) E sA[NPL * BM * LDK];
-  __shared__ __attribute__((aligned(16))) E sB[NPL * BN * LDK];
-  __shared__ int sOut[BM];
-
-  const int2 it = a.items[blockIdx.x];
-  if (it.x < 0) return;
-  const TaskDesc td = a.tasks[it.x];
-  const int m0 = (it.y >> 16) * BM;
-  const int n0 = (it.y & 0xffff) * BN;
+  constexpr int LDK = Smem<PREC, BM, BN>::LDK;
+  using E = typename Smem<PREC, BM, BN>::E;
+  E* sA = sm.sA;
+  E* sB = sm.sB;
+  int* sOut = sm.sOut;
   const int tid = threadIdx.x;
   const int* codes = a.rows + td.idx_off;
   for (int i = tid; i < BM; i += NT) sOut[i] = (m0 + i < td.m) ? codes[td.lda + m0 + i] : ROW_ZERO;
@@ -296,6 +305,16 @@ __device__ __forceinline__ void gemm_tiles(const KArgs& a) {
     }
 }
 
+template <int PREC, int BM, int BN, int WM, int WN, bool ACC>
+__device__ __forceinline__ void gemm_tiles(const KArgs& a) {
+  __shared__ Smem<PREC, BM, BN> sm;
+  const int2 it = a.items[blockIdx.x];
+  if (it.x < 0) return;
+  const TaskDesc td = a.tasks[it.x];
+  tile_body<PREC, BM, BN, WM, WN, ACC>(a, td, (it.y >> 16) * BM, (it.y & 0xffff) * BN, sm);
+}
+
+
 // Entry points with the same body, so that profiles separate the upward pass,
 // the far field, the downward pass and the leaf output.
 template <int PREC, int BM, int BN, int WM, int WN>
@@ -308,13 +327,126 @@ template <int PREC, int BM, int BN, int WM, int WN, bool ACC>
 __global__ __launch_bounds__(NT) void leaf_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, ACC>(a); }
 
 typedef void (*KernelFn)(KArgs);
+
+// ------------------------------------------------------------ batched launch
+// Many compressions in one persistent launch.  Every (instance, step) pair is
+// a stage; stages of one instance run in their evaluation order and stages of
+// different instances are independent.  Work items (tiles) sit in one global
+// queue in stage-major order; each resident block takes the next item, waits
+// until the item's predecessor stage has finished all its tiles, runs the
+// tile, and counts it as done.  Every item's predecessors precede it in the
+// queue and are held by running blocks, so the waits always end; a spin limit
+// still bounds each wait (the block then flags an error and skips the tile).
+struct BInst {
+  const TaskDesc* tasks;
+  const int* rows;
+  const void* A;
+  long long plane;
+  const float* W;
+  long long ldw;
+  float* U;
+  long long ldu;
+  float* WS;
+  long long ldws;
+  int r;
+  int vec;
+};
+
+struct BItem { int inst, stage, task, tile; };   // tile = row tile << 16 | column tile
+
+struct BArgs {
+  const BInst* inst;
+  const BItem* items;
+  int n_items;
+  const int* stage_prev;    // predecessor stage or -1
+  const int* stage_need;    // tiles of the predecessor stage
+  const int* stage_acc;     // 1: the stage accumulates into its output
+  int* done;                // per stage: finished tiles (zero at launch)
+  int* head;                // queue head (zero at launch)
+  int* error;               // set to 1 if a wait exceeded the spin limit
+  long long spin_limit;
+};
+
+template <int PREC, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(NT) void batched_tiles(BArgs b) {
+  __shared__ Smem<PREC, BM, BN> sm;
+  __shared__ int s_item;
+  __shared__ int s_ok;
+  // Lane 0's bookkeeping (publish the previous tile, take the next item, wait
+  // for the item's predecessor stage) sits at the top of the iteration, each
+  // part closed by a barrier, and the values it broadcasts are made
+  // wave-uniform with readfirstlane: the loop's exit and back edge are then
+  // uniform branches, so the compiler cannot split lane 0 from its wave.
+  int last_stage = -1;
+  while (true) {
+    if (threadIdx.x == 0) {
+      if (last_stage >= 0)
+        __hip_atomic_fetch_add(&b.done[last_stage], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      s_item = atomicAdd(b.head, 1);
+    }
+    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(s_item);
+    if (idx >= b.n_items) break;
+    const BItem it = b.items[idx];
+    const int stage = __builtin_amdgcn_readfirstlane(it.stage);
+    if (threadIdx.x == 0) {
+      int ok = 1;
+      const int prev = b.stage_prev[stage];
+      if (prev >= 0) {
+        // Poll with relaxed loads (an acquire on every poll would invalidate
+        // the L2 each time and starve the blocks doing the work), then one
+        // acquire fence once the predecessor stage is complete.
+        const int need = b.stage_need[stage];
+        long long polls = 0;
+        while (__hip_atomic_load(&b.done[prev], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          __builtin_amdgcn_s_sleep(8);
+          if (++polls > b.spin_limit) {
+            atomicExch(b.error, 1);
+            ok = 0;
+            break;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      s_ok = ok;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_ok)) {
+      const BInst& in = b.inst[__builtin_amdgcn_readfirstlane(it.inst)];
+      KArgs a;
+      a.tasks = in.tasks;
+      a.items = nullptr;
+      a.A = in.A;
+      a.plane = in.plane;
+      a.rows = in.rows;
+      a.W = in.W;
+      a.ldw = in.ldw;
+      a.U = in.U;
+      a.ldu = in.ldu;
+      a.WS = in.WS;
+      a.ldws = in.ldws;
+      a.r = in.r;
+      a.vec = in.vec;
+      const TaskDesc td = in.tasks[__builtin_amdgcn_readfirstlane(it.task)];
+      const int tile = __builtin_amdgcn_readfirstlane(it.tile);
+      const int m0 = (tile >> 16) * BM, n0 = (tile & 0xffff) * BN;
+      if (b.stage_acc[stage]) tile_body<PREC, BM, BN, WM, WN, true>(a, td, m0, n0, sm);
+      else tile_body<PREC, BM, BN, WM, WN, false>(a, td, m0, n0, sm);
+    }
+    last_stage = stage;
+    __syncthreads();                      // every thread's stores issued, LDS free
+  }
+}
+
+typedef void (*BatchedFn)(BArgs);
 constexpr int kNumCfg = 6;
 constexpr int kNumFamily = 5;   // n2s, s2s, s2n (accumulate), leaf, leaf accumulating
 struct Cfg { int bm, bn; };
 constexpr Cfg kCfgs[kNumCfg] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}, {128, 32}, {32, 128}};
 
 template <int PREC, int BM, int BN, int WM, int WN>
-void fill_family(KernelFn* row) {
+void fill_family(KernelFn* row, BatchedFn* brow) {
+  *brow = batched_tiles<PREC, BM, BN, WM, WN>;
   row[0] = n2s_tiles<PREC, BM, BN, WM, WN>;
   row[1] = s2s_tiles<PREC, BM, BN, WM, WN>;
   row[2] = s2n_tiles<PREC, BM, BN, WM, WN>;
@@ -322,20 +454,20 @@ void fill_family(KernelFn* row) {
   row[4] = leaf_tiles<PREC, BM, BN, WM, WN, true>;
 }
 
-// table[cfg * kNumFamily + family]
+// table[cfg * kNumFamily + family], batched[cfg]
 template <int PREC>
-void fill_table(KernelFn* table) {
-  fill_family<PREC, 128, 128, 2, 2>(table + 0 * kNumFamily);
-  fill_family<PREC, 128, 64, 2, 2>(table + 1 * kNumFamily);
-  fill_family<PREC, 64, 128, 2, 2>(table + 2 * kNumFamily);
-  fill_family<PREC, 64, 64, 2, 2>(table + 3 * kNumFamily);
-  fill_family<PREC, 128, 32, 4, 1>(table + 4 * kNumFamily);
-  fill_family<PREC, 32, 128, 1, 4>(table + 5 * kNumFamily);
+void fill_table(KernelFn* table, BatchedFn* batched) {
+  fill_family<PREC, 128, 128, 2, 2>(table + 0 * kNumFamily, batched + 0);
+  fill_family<PREC, 128, 64, 2, 2>(table + 1 * kNumFamily, batched + 1);
+  fill_family<PREC, 64, 128, 2, 2>(table + 2 * kNumFamily, batched + 2);
+  fill_family<PREC, 64, 64, 2, 2>(table + 3 * kNumFamily, batched + 3);
+  fill_family<PREC, 128, 32, 4, 1>(table + 4 * kNumFamily, batched + 4);
+  fill_family<PREC, 32, 128, 1, 4>(table + 5 * kNumFamily, batched + 5);
 }
 
-void kernels_f32(KernelFn* table);
-void kernels_bf16(KernelFn* table);
-void kernels_x3(KernelFn* table);
+void kernels_f32(KernelFn* table, BatchedFn* batched);
+void kernels_bf16(KernelFn* table, BatchedFn* batched);
+void kernels_x3(KernelFn* table, BatchedFn* batched);
 
 }  // namespace dev
 }  // namespace gofmm

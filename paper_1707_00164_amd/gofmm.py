@@ -63,6 +63,11 @@ SIGNATURES = [
     ("gofmm_evaluate_batched", C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_void_p]),
+    ("gofmm_autotune_batched", C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_void_p]),
+    ("gofmm_batched_status", C.c_int, [C.POINTER(C.c_int32)]),
+    ("gofmm_batched_spin_limit", C.c_int, [C.c_int64]),
     ("gofmm_launch_count", C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     ("gofmm_launch_info", C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_int64)]),
@@ -255,8 +260,8 @@ class Compression:
             self.h = None
 
 
-def evaluate_batched(comps: Sequence[Compression], Ws, Us=None, stream=None):
-    """U_i = K~_i W_i for every i in one call."""
+def evaluate_batched(comps: Sequence[Compression], Ws, Us=None, stream=None, autotune=False):
+    """U_i = K~_i W_i for every i in one persistent launch."""
     import torch
     k = len(comps)
     if Us is None:
@@ -267,5 +272,17 @@ def evaluate_batched(comps: Sequence[Compression], Ws, Us=None, stream=None):
     lw = (C.c_int64 * k)(*[w.stride(0) for w in Ws])
     up = (C.c_void_p * k)(*[_ptr(u) for u in Us])
     lu = (C.c_int64 * k)(*[u.stride(0) for u in Us])
-    _check(lib().gofmm_evaluate_batched(k, hs, rs, wp, lw, up, lu, _stream(stream)))
+    fn = lib().gofmm_autotune_batched if autotune else lib().gofmm_evaluate_batched
+    _check(fn(k, hs, rs, wp, lw, up, lu, _stream(stream)))
     return Us
+
+
+def batched_status() -> int:
+    """1 if a dependency wait of the last batched launch hit its spin limit."""
+    e = C.c_int32()
+    _check(lib().gofmm_batched_status(C.byref(e)))
+    return int(e.value)
+
+
+def batched_spin_limit(polls: int):
+    _check(lib().gofmm_batched_spin_limit(polls))
