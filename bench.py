@@ -115,6 +115,195 @@ def cpu_baseline(comp, w, pts, W64, U_gpu_rows, rows, torch):
     return res, ref, exact
 
 
+def _timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def form_batched(args):
+    """48 compressions of uneven N (log-uniform in [8192, 131072]) in one
+    persistent launch per step, r in {32, 64, 128, 256}."""
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1707_00164_amd as g
+    insts = workloads.batched_instances(args.instances)
+    comps, Ws, Us = [], [], []
+    t0 = time.perf_counter()
+    for w in insts:
+        pts = workloads.points(w)
+        S = g.KernelSampler(pts, w.kernel, w.h, w.shift)
+        comps.append(g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol,
+                                            kappa=w.kappa, budget=w.budget, seed=w.seed))
+        Ws.append(torch.from_numpy(workloads.rhs(w.n, w.r, w.seed).astype(np.float32)).cuda())
+        Us.append(torch.empty_like(Ws[-1]))
+    t_comp = time.perf_counter() - t0
+    log(f"compressed {len(insts)} instances (sum N {sum(w.n for w in insts)}) in {t_comp:.1f} s")
+    for c, W, U in zip(comps, Ws, Us):
+        c.prepare(W.shape[1])
+    g.evaluate_batched(comps, Ws, Us, autotune=True)
+    sec = _timed(lambda: g.evaluate_batched(comps, Ws, Us), args.steps, args.warmup, torch)
+    assert g.batched_status() == 0
+    seq = _timed(lambda: [c.evaluate(W, U) for c, W, U in zip(comps, Ws, Us)], args.steps, args.warmup, torch)
+    flops = sum(c.stats().flops_per_rhs * W.shape[1] for c, W in zip(comps, Ws))
+    dense = sum(2.0 * w.n * w.n * w.r for w in insts)
+    opb = sum(c.stats().operator_bytes for c in comps)
+    io = sum(2 * 4 * w.n * w.r for w in insts)
+    t_roof = max(flops / (PEAK_TFLOPS["f32"] * 1e12), (opb + io) / (HBM_GBS * 1e9))
+    out = {"metric": METRIC, "form": "batched", "value": round(dense / sec / 1e9, 2), "unit": "GFLOP/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"batched{len(insts)}_loguniform_8192_131072", "instances": len(insts),
+                      "sum_n": sum(w.n for w in insts), "r": sorted({w.r for w in insts})},
+           "algorithmic_tflops": round(flops / sec / 1e12, 3),
+           "sequential_ms_per_step": round(seq * 1e3, 4), "speedup_vs_sequential": round(seq / sec, 3),
+           "roofline": {"bound": "time", "t_roof_ms": round(t_roof * 1e3, 4), "frac": round(t_roof / sec, 4),
+                        "flops": flops, "bytes": opb + io,
+                        "note": "max(flops / FP32 matrix-core peak, operator + W + U bytes / 8 TB/s)"},
+           "compress_seconds": round(t_comp, 1)}
+    print(json.dumps(out), flush=True)
+
+
+def form_large(args):
+    """N=262144 inverse multiquadric, m = s = 512, tau 1e-6: FP32, BF16 and
+    split-BF16 storage of the same structure, r = 1024 and 2048; error against
+    the FP64 oracle on 64 sampled rows."""
+    import numpy as np
+    import tempfile
+    import torch
+    import workloads
+    import paper_1707_00164_amd as g
+    w = workloads.large_imq()
+    pts = workloads.points(w)
+    S = g.KernelSampler(pts, w.kernel, w.h, w.shift)
+    t0 = time.perf_counter()
+    base = g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol, kappa=w.kappa,
+                                  budget=w.budget, seed=w.seed)
+    t_comp = time.perf_counter() - t0
+    st = base.stats()
+    log(f"compressed N={w.n} in {t_comp:.1f} s: mean rank {st.rank_sum / (st.n_nodes - 1):.1f}, "
+        f"{st.flops_per_rhs:.3e} flops per rhs, operator {st.operator_bytes / 1e9:.2f} GB")
+    fd, path = tempfile.mkstemp(suffix=".gofmm")
+    os.close(fd)
+    base.export(path)
+    rows = workloads.sample_rows(w.n, 64, w.seed)
+    res = {}
+    ref_rows = {}
+    forms = [("fp32", g.FP32, g.FP32), ("bf16", g.BF16, g.FP32), ("bf16x3", g.BF16X3, g.BF16X3)]
+    for r in args.r_list:
+        W = torch.from_numpy(workloads.rhs(w.n, r, w.seed).astype(np.float32)).cuda()
+        U = torch.empty_like(W)
+        for name, sp, sn in forms:
+            c = base if name == "fp32" else g.Compression.load(path, S, storage=sp, near_storage=sn)
+            c.prepare(r)
+            c.autotune(W, U)
+            sec, prof = time_steps(c, W, U, args.steps, args.warmup, torch, profile=True)
+            rl = roofline(c, prof, r, args.steps, "f32" if name == "fp32" else "bf16")
+            res[f"{name}_r{r}"] = {"ms_per_step": round(sec * 1e3, 3),
+                                   "value": round(2.0 * w.n * w.n * r / sec / 1e9, 1),
+                                   "algorithmic_tflops": round(st.flops_per_rhs * r / sec / 1e12, 2),
+                                   "roofline": rl, "rows": U.cpu().numpy()[rows].astype(np.float64)}
+            log(f"{name} r={r}: {sec * 1e3:.2f} ms, dominant {rl['kernel']} {rl['achieved']} TFLOP/s")
+            if c is not base:
+                c.free()
+                torch.cuda.empty_cache()
+        if not args.no_cpu_baseline:
+            from oracle import cfile, dense, evaluate, kernels
+            cc = cfile.read(path)
+            K = kernels.KernelMatrix(pts, w.kernel, w.h, w.shift)
+            W64 = W.cpu().numpy().astype(np.float64)
+            t1 = time.perf_counter()
+            ref = evaluate.tree_walk(cc, K, W64, rows)
+            t_or = time.perf_counter() - t1
+            exact = dense.kw(K, W64, rows)
+            for name, _, _ in forms:
+                x = res[f"{name}_r{r}"]
+                x["gpu_vs_oracle_same_compression"] = float(np.linalg.norm(x["rows"] - ref) / np.linalg.norm(ref))
+                x["eps2_vs_exact_KW"] = float(np.linalg.norm(x["rows"] - exact) / np.linalg.norm(exact))
+            res[f"oracle_r{r}_seconds"] = round(t_or, 2)
+        del W, U
+        torch.cuda.empty_cache()
+    os.unlink(path)
+    for k in list(res):
+        if isinstance(res[k], dict):
+            res[k].pop("rows", None)
+    out = {"metric": METRIC, "form": "large", "unit": "GFLOP/s", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": w.name, "n": w.n, "leaf_size": w.leaf_size, "max_rank": w.max_rank,
+                      "tol": w.tol, "budget": w.budget, "r": args.r_list},
+           "compress_seconds": round(t_comp, 1), "mean_rank": st.rank_sum / (st.n_nodes - 1),
+           "flops_per_rhs": st.flops_per_rhs, "operator_gb": st.operator_bytes / 1e9, "results": res}
+    print(json.dumps(out), flush=True)
+
+
+def form_serving(args):
+    """Resident compressions, Poisson requests with r uniform in [1, 512]."""
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1707_00164_amd as g
+    ws = [w for w in workloads.serving_instances(args.instances) if w.n <= args.max_n]
+    comps = []
+    t0 = time.perf_counter()
+    for w in ws:
+        pts = workloads.points(w)
+        S = g.KernelSampler(pts, w.kernel, w.h, w.shift)
+        comps.append(g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol,
+                                            kappa=w.kappa, budget=w.budget, seed=w.seed))
+    t_comp = time.perf_counter() - t0
+    log(f"compressed {len(ws)} models in {t_comp:.1f} s")
+    rmax = 512
+    srv = g.Server(hbm_budget_bytes=args.hbm_gb << 30, streams=args.streams, max_batch=len(ws))
+    ids = [srv.add(c, rmax) for c in comps]
+    rng = np.random.default_rng(7)
+    pool = {}
+    for i, w in enumerate(ws):       # a few resident input blocks per model
+        pool[i] = [torch.from_numpy(workloads.rhs(w.n, rmax, w.seed + k).astype(np.float32)).cuda()
+                   for k in range(2)]
+    torch.cuda.synchronize()
+
+    def run(n_req, qps):
+        srv.reset_stats()
+        hs = []
+        outs = []
+        t_next = time.perf_counter()
+        for q in range(n_req):
+            i = int(rng.integers(0, len(ws)))
+            r = int(rng.integers(1, rmax + 1))
+            W = pool[i][q % 2][:, :r]
+            U = torch.empty((ws[i].n, r), device="cuda")
+            if qps:
+                t_next += rng.exponential(1.0 / qps)
+                while time.perf_counter() < t_next:
+                    pass
+            hs.append(srv.submit(ids[i], W, U))
+            outs.append(U)
+        for h in hs:
+            srv.wait(h, timeout_ms=120000)
+        st = srv.stats()
+        return {"requests": n_req, "qps_offered": qps, "throughput_rps": round(st.completed / (st.elapsed_ms / 1e3), 1),
+                "columns_per_s": round(st.columns / (st.elapsed_ms / 1e3), 1), "p50_ms": round(st.p50_ms, 3),
+                "p99_ms": round(st.p99_ms, 3), "mean_ms": round(st.mean_ms, 3), "batches": st.batches,
+                "failed": st.failed}
+    run(64, 0)                                     # warm-up (autotune-free path)
+    sat = run(args.requests, 0)                    # burst: saturation throughput
+    log(f"saturation: {sat}")
+    res = {"saturation": sat}
+    for frac in (0.5, 0.9):
+        res[f"poisson_{int(frac * 100)}pct"] = run(args.requests, frac * sat["throughput_rps"])
+        log(f"poisson {frac}: {res[f'poisson_{int(frac * 100)}pct']}")
+    srv.close()
+    out = {"metric": METRIC, "form": "serving", "unit": "ms", "n_gpus": 1, "data": "synthetic",
+           "config": {"models": len(ws), "n": [w.n for w in ws], "r": "uniform 1..512", "streams": args.streams},
+           "compress_seconds": round(t_comp, 1), "results": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +313,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--rows", type=int, default=256, help="rows in the oracle sample")
+    ap.add_argument("--form", default="flat", choices=["flat", "batched", "serving", "large"],
+                    help="flat: the N=65536 workload (default); batched: 48 compressions in one launch; "
+                         "serving: request loop with p50/p99; large: N=262144 in three precisions")
+    ap.add_argument("--instances", type=int, default=48)
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--streams", type=int, default=2)
+    ap.add_argument("--hbm-gb", type=int, default=64)
+    ap.add_argument("--max-n", type=int, default=262144)
+    ap.add_argument("--r-list", type=int, nargs="+", default=[1024, 2048])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU only; every box here has one "
@@ -138,6 +336,9 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     g.lib()
+    if args.form != "flat":
+        {"batched": form_batched, "serving": form_serving, "large": form_large}[args.form](args)
+        return
     w = workloads.clustered_gaussian()
     pts = workloads.points(w)
     S = g.KernelSampler(pts, w.kernel, w.h, w.shift)

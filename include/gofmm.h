@@ -39,7 +39,8 @@ enum {
   GOFMM_ENOMEM = -4,     /* host or device allocation failed */
   GOFMM_EHIP = -5,       /* a HIP runtime error (message in last_error) */
   GOFMM_EIO = -6,        /* file could not be read or written / bad format */
-  GOFMM_ELIMIT = -7      /* a documented size limit was exceeded */
+  GOFMM_ELIMIT = -7,     /* a documented size limit was exceeded */
+  GOFMM_ETIMEDOUT = -8   /* a wait ended before the awaited work finished */
 };
 
 /* distance used for the tree and the neighbours (Sec. 2.1) */
@@ -220,6 +221,68 @@ void gofmm_free(gofmm_compression* c);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* gofmm_last_error(void);
+
+/* ------------------------------------------------------------- serving
+ * A request loop on its own host thread.  Compressions ("models") stay
+ * resident on the current device; a model is admitted, in the order added,
+ * once its footprint (gofmm_footprint for r_max plus two n x r_max FP32
+ * staging blocks) fits the HBM budget next to the models already resident,
+ * and its requests wait until then.  Requests U = K~ W for a model may be
+ * submitted at any time from any thread.  Whenever one of the server's
+ * streams is free, every resident model with pending requests and no work in
+ * flight joins one batched persistent launch (at most max_batch models, one
+ * storage precision); a model's pending requests are packed side by side as
+ * columns (at most r_max in total), so requests that arrive while others run
+ * are admitted as streams and models free up.  A request's result is the same
+ * as its standalone evaluate, whatever it was batched with.
+ */
+typedef struct gofmm_server gofmm_server;
+
+typedef struct {
+  int64_t completed, failed, pending, inflight, models, admit_queue;
+  int64_t batches;            /* batched launches made */
+  int64_t columns;            /* right-hand sides evaluated */
+  int64_t packed;             /* model launches that packed several requests */
+  int64_t hbm_used, hbm_budget;
+  double p50_ms, p99_ms, mean_ms, max_ms;   /* latency, submit to completion */
+  double elapsed_ms;          /* since creation or the last reset */
+} gofmm_server_stats_t;
+
+/* Start a server with `streams` concurrent batches (1..16) on the current
+ * device.  The server owns its streams and staging; not its compressions. */
+int gofmm_server_create(int64_t hbm_budget_bytes, int32_t streams, int32_t max_batch,
+                        gofmm_server** out);
+
+/* Serve compression c for requests of up to r_max right-hand sides.  c must
+ * stay alive until removed; while served, its device memory belongs to the
+ * server.  GOFMM_ENOMEM if its footprint alone exceeds the budget. */
+int gofmm_server_add(gofmm_server* s, gofmm_compression* c, int64_t r_max, int32_t* model);
+
+/* Wait for the model's work in flight, fail its pending requests, release its
+ * device memory (the compression itself stays valid). */
+int gofmm_server_remove(gofmm_server* s, int32_t model);
+
+/* Enqueue U = K~ W (device arrays as for gofmm_evaluate, 1 <= r <= r_max).
+ * W must already hold its values (the server's streams do not wait on the
+ * caller's streams); W and U must stay valid and untouched until the request
+ * completes. */
+int gofmm_server_submit(gofmm_server* s, int32_t model, int64_t r, const float* W, int64_t ldw,
+                        float* U, int64_t ldu, int64_t* request);
+
+/* Block until the request completes (at most timeout_ms; <= 0 waits without
+ * bound); its latency in ms.  The request id is then retired.  A failed
+ * request returns GOFMM_EHIP with the reason; GOFMM_ETIMEDOUT leaves it
+ * pending (wait again or test later). */
+int gofmm_server_wait(gofmm_server* s, int64_t request, int64_t timeout_ms, double* latency_ms);
+
+/* Non-blocking: *done = 1 (and the id is retired) if the request completed. */
+int gofmm_server_test(gofmm_server* s, int64_t request, int32_t* done, double* latency_ms);
+
+int gofmm_server_stats(gofmm_server* s, gofmm_server_stats_t* out);
+int gofmm_server_reset_stats(gofmm_server* s);
+
+/* Finish all submitted work, release every model's device memory, stop. */
+void gofmm_server_destroy(gofmm_server* s);
 
 /* ------------------------------------------------ synthetic kernel sampler
  * A ready-made thread-safe sampler for radial kernels over a point cloud the

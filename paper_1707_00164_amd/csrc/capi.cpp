@@ -26,9 +26,6 @@ void device_profile_read(Compression& c, int n, float* total_ms, int* calls);
 
 }  // namespace gofmm
 
-struct gofmm_compression {
-  gofmm::Compression c;
-};
 
 using namespace gofmm;
 

@@ -29,6 +29,7 @@
 #include <cstdlib>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -394,54 +395,11 @@ i64 device_footprint(const Compression& c, i64 r_max) {
 }
 
 // ------------------------------------------------------------------ batched launch
-struct BatchPlan;
-static BatchPlan*& last_batch() {
-  static BatchPlan* p = nullptr;
-  return p;
-}
 static long long& spin_limit_ref() {
   static long long v = 1ll << 21;
   return v;
 }
-static long long batch_spin_limit() { return spin_limit_ref(); }
 void device_set_spin_limit(long long v) { spin_limit_ref() = v > 0 ? v : (1ll << 21); }
-
-struct BatchPlan {
-  std::vector<uint64_t> key;     // compression ids and r values, then the configuration
-  int prec = 0, cfg = 0;
-  dev::BItem* items = nullptr;
-  int n_items = 0;
-  int* stage_tab = nullptr;      // prev, need, acc (3 x n_stages)
-  int n_stages = 0;
-  int* counters = nullptr;       // done[n_stages], head, error
-  dev::BInst* inst = nullptr;
-  int k = 0;
-  int grid = 0;
-  ~BatchPlan() {
-    (void)hipFree(items);
-    (void)hipFree(stage_tab);
-    (void)hipFree(counters);
-    (void)hipFree(inst);
-  }
-};
-
-static std::vector<std::unique_ptr<BatchPlan>>& batch_cache() {
-  static std::vector<std::unique_ptr<BatchPlan>> c;   // most recent last
-  return c;
-}
-static std::map<std::vector<uint64_t>, int>& batch_tuned() {
-  static std::map<std::vector<uint64_t>, int> t;
-  return t;
-}
-
-static std::vector<uint64_t> batch_key(int k, Compression* const* c, const i64* r) {
-  std::vector<uint64_t> key;
-  for (int i = 0; i < k; ++i) {
-    key.push_back(c[i]->uid);
-    key.push_back((uint64_t)r[i]);
-  }
-  return key;
-}
 
 static int batch_prec(int k, Compression* const* c) {
   int prec = -1;
@@ -454,33 +412,29 @@ static int batch_prec(int k, Compression* const* c) {
   return prec < 0 ? PREC_F32 : prec;
 }
 
+int device_batch_precision(Compression& c) {
+  Compression* p = &c;
+  return batch_prec(1, &p);
+}
+
 // Stage-major queue: stage j of every instance precedes stage j + 1 of any;
-// within a stage position, tiles are ordered longest-k first.
-static BatchPlan* batch_plan(int k, Compression* const* c, const i64* r, int cfg) {
-  std::vector<uint64_t> key = batch_key(k, c, r);
-  key.push_back((uint64_t)cfg);
-  auto& cache = batch_cache();
-  for (size_t i = 0; i < cache.size(); ++i)
-    if (cache[i]->key == key) {
-      std::unique_ptr<BatchPlan> p = std::move(cache[i]);
-      cache.erase(cache.begin() + i);
-      cache.push_back(std::move(p));
-      return cache.back().get();
-    }
-  std::unique_ptr<BatchPlan> bp(new BatchPlan);
-  bp->key = key;
-  bp->prec = batch_prec(k, c);
-  bp->cfg = cfg;
-  bp->k = k;
+// within a stage position, tiles are ordered longest-k first.  need[s] is the
+// tile count of stage s's predecessor.
+static void build_batch_tables(int k, Compression* const* c, const i64* r, int cfg, std::vector<dev::BItem>& items,
+                               std::vector<int>& prev, std::vector<int>& need, std::vector<int>& acc) {
   const Cfg& g = kCfgs[cfg];
-  std::vector<int> prev, need, acc;
-  std::vector<std::vector<int>> stage_of(k);   // stage id of instance i's j-th launch
+  items.clear();
+  prev.clear();
+  need.clear();
+  acc.clear();
+  std::vector<int> own;
+  std::vector<int> last(k, -1);
   size_t max_l = 0;
   for (int i = 0; i < k; ++i) max_l = std::max(max_l, c[i]->plan.launches.size());
-  std::vector<dev::BItem> items;
+  struct T { dev::BItem it; i64 cost; };
+  std::vector<T> pos;
   for (size_t j = 0; j < max_l; ++j) {
-    struct T { dev::BItem it; i64 cost; };
-    std::vector<T> pos;
+    pos.clear();
     for (int i = 0; i < k; ++i) {
       const HostPlan& pl = c[i]->plan;
       if (j >= pl.launches.size()) continue;
@@ -494,45 +448,16 @@ static BatchPlan* batch_plan(int k, Compression* const* c, const i64* r, int cfg
             pos.push_back({{i, sid, t, (mt << 16) | nt}, (i64)std::max(pl.tasks[t].lda, 32)});
             ++count;
           }
-      const int ps = j == 0 ? -1 : stage_of[i][j - 1];
-      prev.push_back(ps);
-      need.push_back(ps < 0 ? 0 : 0);
+      prev.push_back(last[i]);
+      own.push_back(count);
       acc.push_back(l.accumulate);
-      stage_of[i].push_back(sid);
-      // remember the tile count of this stage for its successor's wait
-      need.back() = count;          // temporarily the stage's own count
+      last[i] = sid;
     }
     std::stable_sort(pos.begin(), pos.end(), [](const T& x, const T& y) { return x.cost > y.cost; });
     for (auto& t : pos) items.push_back(t.it);
   }
-  // need[s] must be the tile count of prev[s]; convert from own counts
-  std::vector<int> own(need);
+  need.resize(prev.size());
   for (size_t s2 = 0; s2 < prev.size(); ++s2) need[s2] = prev[s2] < 0 ? 0 : own[prev[s2]];
-  bp->n_stages = (int)prev.size();
-  bp->n_items = (int)items.size();
-  std::vector<int> tab(prev);
-  tab.insert(tab.end(), need.begin(), need.end());
-  tab.insert(tab.end(), acc.begin(), acc.end());
-  if (!items.empty()) {
-    HIP_OK(hipMalloc((void**)&bp->items, items.size() * sizeof(dev::BItem)));
-    HIP_OK(hipMemcpy(bp->items, items.data(), items.size() * sizeof(dev::BItem), hipMemcpyHostToDevice));
-  }
-  HIP_OK(hipMalloc((void**)&bp->stage_tab, std::max<size_t>(1, tab.size()) * sizeof(int)));
-  if (!tab.empty()) HIP_OK(hipMemcpy(bp->stage_tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
-  HIP_OK(hipMalloc((void**)&bp->counters, (bp->n_stages + 2) * sizeof(int)));
-  HIP_OK(hipMalloc((void**)&bp->inst, k * sizeof(dev::BInst)));
-  dev::BatchedFn fn = tables().b[bp->prec][cfg];
-  int per_cu = 0, cus = 0, devid = 0;
-  HIP_OK(hipGetDevice(&devid));
-  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, dev::NT, 0));
-  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
-  bp->grid = std::max(1, std::min(bp->n_items, std::max(1, per_cu) * std::max(1, cus)));
-  if (cache.size() >= 16) {
-    if (last_batch() == cache.front().get()) last_batch() = nullptr;
-    cache.erase(cache.begin());
-  }
-  cache.push_back(std::move(bp));
-  return cache.back().get();
 }
 
 static int batch_cfg_model(int k, Compression* const* c, const i64* r) {
@@ -551,12 +476,80 @@ static int batch_cfg_model(int k, Compression* const* c, const i64* r) {
   return bc;
 }
 
-static void batch_launch(BatchPlan* bp, int k, Compression* const* c, const i64* r, const float* const* W,
-                         const i64* ldw, float* const* U, const i64* ldu, hipStream_t st) {
-  std::vector<dev::BInst> in(k);
+static int batch_grid_cap(int prec, int cfg) {
+  static std::map<std::pair<int, int>, int> cache;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find({prec, cfg});
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0, devid = 0;
+  HIP_OK(hipGetDevice(&devid));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tables().b[prec][cfg], dev::NT, 0));
+  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
+  const int cap = std::max(1, per_cu) * std::max(1, cus);
+  cache[{prec, cfg}] = cap;
+  return cap;
+}
+
+BatchRing::~BatchRing() {
+  for (auto& s : slot) {
+    if (s.ev) (void)hipEventSynchronize((hipEvent_t)s.ev);
+    (void)hipFree(s.dev);
+    (void)hipHostFree(s.host);
+    if (s.ev) (void)hipEventDestroy((hipEvent_t)s.ev);
+  }
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// One batched launch through a staging slot: the host tables go to pinned
+// memory, one async copy moves them (with the zeroed counters) to the device,
+// the kernel runs, and the error flag is copied back to pinned memory.
+void ring_launch(BatchRing& ring, int k, Compression* const* c, const i64* r, const float* const* W,
+                 const i64* ldw, float* const* U, const i64* ldu, hipStream_t st, int cfg) {
+  const int prec = batch_prec(k, c);
+  std::vector<dev::BItem> items;
+  std::vector<int> prev, need, acc;
+  build_batch_tables(k, c, r, cfg, items, prev, need, acc);
+  const int ns = (int)prev.size();
+  const size_t o_cnt = 0, n_cnt = (size_t)(ns + 2) * sizeof(int);
+  const size_t o_tab = align256(o_cnt + n_cnt), n_tab = (size_t)3 * ns * sizeof(int);
+  const size_t o_inst = align256(o_tab + n_tab), n_inst = (size_t)k * sizeof(dev::BInst);
+  const size_t o_item = align256(o_inst + n_inst), n_item = items.size() * sizeof(dev::BItem);
+  const size_t o_err = align256(o_item + n_item);
+  const size_t total = o_err + 256;
+  BatchRing::Slot& s = ring.slot[ring.next];
+  const int si = ring.next;
+  ring.next = (ring.next + 1) % BatchRing::NS;
+  if (s.ev) {
+    HIP_OK(hipEventSynchronize((hipEvent_t)s.ev));     // the slot's previous launch has ended
+  } else {
+    hipEvent_t ev;
+    HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    s.ev = ev;
+  }
+  if (total > s.cap) {
+    (void)hipFree(s.dev);
+    (void)hipHostFree(s.host);
+    s.dev = nullptr;
+    s.host = nullptr;
+    s.cap = 0;
+    const size_t cap = total + total / 2;
+    HIP_OK(hipMalloc((void**)&s.dev, cap));
+    HIP_OK(hipHostMalloc((void**)&s.host, cap, hipHostMallocDefault));
+    s.cap = cap;
+  }
+  char* h = s.host;
+  std::memset(h + o_cnt, 0, n_cnt);
+  int* tab = reinterpret_cast<int*>(h + o_tab);
+  for (int q = 0; q < ns; ++q) {
+    tab[q] = prev[q];
+    tab[ns + q] = need[q];
+    tab[2 * ns + q] = acc[q];
+  }
+  dev::BInst* in = reinterpret_cast<dev::BInst*>(h + o_inst);
   for (int i = 0; i < k; ++i) {
     DeviceState* d = c[i]->dev;
-    const int prec = bp->prec;
     in[i].tasks = d->tasks;
     in[i].rows = d->rows;
     in[i].A = prec == PREC_F32 ? (const void*)d->a_f32 : prec == PREC_BF16 ? (const void*)d->a_b16 : (const void*)d->a_x3;
@@ -570,26 +563,41 @@ static void batch_launch(BatchPlan* bp, int k, Compression* const* c, const i64*
     in[i].r = (int)r[i];
     in[i].vec = ((uintptr_t)W[i] % 16 == 0) && ((uintptr_t)U[i] % 16 == 0) && ldw[i] % 4 == 0 && ldu[i] % 4 == 0;
   }
-  HIP_OK(hipMemcpyAsync(bp->inst, in.data(), k * sizeof(dev::BInst), hipMemcpyHostToDevice, st));
-  HIP_OK(hipMemsetAsync(bp->counters, 0, (bp->n_stages + 2) * sizeof(int), st));
-  if (bp->n_items == 0) return;
-  dev::BArgs a;
-  a.inst = bp->inst;
-  a.items = bp->items;
-  a.n_items = bp->n_items;
-  a.stage_prev = bp->stage_tab;
-  a.stage_need = bp->stage_tab + bp->n_stages;
-  a.stage_acc = bp->stage_tab + 2 * bp->n_stages;
-  a.done = bp->counters;
-  a.head = bp->counters + bp->n_stages;
-  a.error = bp->counters + bp->n_stages + 1;
-  a.spin_limit = batch_spin_limit();
-  hipLaunchKernelGGL(tables().b[bp->prec][bp->cfg], dim3(bp->grid), dim3(dev::NT), 0, st, a);
-  HIP_OK(hipGetLastError());
-  last_batch() = bp;
+  if (n_item) std::memcpy(h + o_item, items.data(), n_item);
+  *reinterpret_cast<int*>(h + o_err) = 0;
+  HIP_OK(hipMemcpyAsync(s.dev, h, o_err, hipMemcpyHostToDevice, st));
+  if (!items.empty()) {
+    dev::BArgs a;
+    char* dv = s.dev;
+    a.inst = reinterpret_cast<const dev::BInst*>(dv + o_inst);
+    a.items = reinterpret_cast<const dev::BItem*>(dv + o_item);
+    a.n_items = (int)items.size();
+    a.stage_prev = reinterpret_cast<const int*>(dv + o_tab);
+    a.stage_need = a.stage_prev + ns;
+    a.stage_acc = a.stage_prev + 2 * ns;
+    a.done = reinterpret_cast<int*>(dv + o_cnt);
+    a.head = a.done + ns;
+    a.error = a.done + ns + 1;
+    a.spin_limit = spin_limit_ref();
+    const int grid = std::max(1, std::min(a.n_items, batch_grid_cap(prec, cfg)));
+    hipLaunchKernelGGL(tables().b[prec][cfg], dim3(grid), dim3(dev::NT), 0, st, a);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(h + o_err, dv + o_cnt + (size_t)(ns + 1) * sizeof(int), sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  HIP_OK(hipEventRecord((hipEvent_t)s.ev, st));
+  s.err_off = o_err;
+  ring.last = si;
 }
 
-static void batch_prepare(int k, Compression* const* c, const i64* r) {
+// Error flag of the ring's last launch (waits for it).
+int ring_status(BatchRing& ring) {
+  if (ring.last < 0) return 0;
+  BatchRing::Slot& s = ring.slot[ring.last];
+  HIP_OK(hipEventSynchronize((hipEvent_t)s.ev));
+  return *reinterpret_cast<int*>(s.host + s.err_off);
+}
+
+void batch_prepare(int k, Compression* const* c, const i64* r) {
   int cur;
   HIP_OK(hipGetDevice(&cur));
   for (int i = 0; i < k; ++i) {
@@ -599,54 +607,76 @@ static void batch_prepare(int k, Compression* const* c, const i64* r) {
   }
 }
 
+static std::vector<uint64_t> batch_key(int k, Compression* const* c, const i64* r) {
+  std::vector<uint64_t> key;
+  for (int i = 0; i < k; ++i) {
+    key.push_back(c[i]->uid);
+    key.push_back((uint64_t)r[i]);
+  }
+  return key;
+}
+
+static std::mutex& api_mutex() {
+  static std::mutex m;
+  return m;
+}
+static BatchRing& api_ring() {
+  static BatchRing* r = new BatchRing;   // lives until the process ends
+  return *r;
+}
+static std::map<std::vector<uint64_t>, int>& batch_tuned() {
+  static std::map<std::vector<uint64_t>, int> t;
+  return t;
+}
+
 // All instances' steps in one persistent launch.
 void device_evaluate_batched(int k, Compression* const* c, const i64* r, const float* const* W,
                              const i64* ldw, float* const* U, const i64* ldu, void* stream) {
+  std::lock_guard<std::mutex> g(api_mutex());
   batch_prepare(k, c, r);
   auto it = batch_tuned().find(batch_key(k, c, r));
   const int cfg = it != batch_tuned().end() ? it->second : batch_cfg_model(k, c, r);
-  BatchPlan* bp = batch_plan(k, c, r, cfg);
-  batch_launch(bp, k, c, r, W, ldw, U, ldu, (hipStream_t)stream);
+  ring_launch(api_ring(), k, c, r, W, ldw, U, ldu, (hipStream_t)stream, cfg);
 }
 
 // Time the whole batched launch with every tile configuration; keep the fastest.
 void device_autotune_batched(int k, Compression* const* c, const i64* r, const float* const* W,
                              const i64* ldw, float* const* U, const i64* ldu, void* stream, int reps) {
-  batch_prepare(k, c, r);
-  hipStream_t st = (hipStream_t)stream;
-  hipEvent_t e0, e1;
-  HIP_OK(hipEventCreate(&e0));
-  HIP_OK(hipEventCreate(&e1));
-  float best = 1e30f;
-  int bc = batch_cfg_model(k, c, r);
-  for (int q = 0; q < kNumCfg; ++q) {
-    BatchPlan* bp = batch_plan(k, c, r, q);
-    batch_launch(bp, k, c, r, W, ldw, U, ldu, st);
-    HIP_OK(hipEventRecord(e0, st));
-    for (int t = 0; t < reps; ++t) batch_launch(bp, k, c, r, W, ldw, U, ldu, st);
-    HIP_OK(hipEventRecord(e1, st));
-    HIP_OK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-    if (std::getenv("GOFMM_TUNE_LOG"))
-      std::fprintf(stderr, "tune batched k=%d cfg %dx%d: %.4f ms\n", k, kCfgs[q].bm, kCfgs[q].bn, ms / reps);
-    if (ms < best) { best = ms; bc = q; }
+  {
+    std::lock_guard<std::mutex> g(api_mutex());
+    batch_prepare(k, c, r);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bc = batch_cfg_model(k, c, r);
+    for (int q = 0; q < kNumCfg; ++q) {
+      ring_launch(api_ring(), k, c, r, W, ldw, U, ldu, st, q);
+      HIP_OK(hipEventRecord(e0, st));
+      for (int t = 0; t < reps; ++t) ring_launch(api_ring(), k, c, r, W, ldw, U, ldu, st, q);
+      HIP_OK(hipEventRecord(e1, st));
+      HIP_OK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      if (std::getenv("GOFMM_TUNE_LOG"))
+        std::fprintf(stderr, "tune batched k=%d cfg %dx%d: %.4f ms\n", k, kCfgs[q].bm, kCfgs[q].bn, ms / reps);
+      if (ms < best) { best = ms; bc = q; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    batch_tuned()[batch_key(k, c, r)] = bc;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  batch_tuned()[batch_key(k, c, r)] = bc;
   device_evaluate_batched(k, c, r, W, ldw, U, ldu, stream);
 }
 
-// Waits for the device, then reports and clears the error flag of the last
-// batched launch (1 if a dependency wait hit its spin limit).
+// Waits for the last batched launch made through the API and reports its
+// error flag (1 if a dependency wait hit its poll bound).
 int device_batched_status() {
-  BatchPlan* bp = last_batch();
-  if (!bp) return 0;
-  HIP_OK(hipDeviceSynchronize());
-  int flag = 0;
-  HIP_OK(hipMemcpy(&flag, bp->counters + bp->n_stages + 1, sizeof(int), hipMemcpyDeviceToHost));
-  return flag;
+  std::lock_guard<std::mutex> g(api_mutex());
+  return ring_status(api_ring());
 }
+
+int device_batch_cfg(int k, Compression* const* c, const i64* r) { return batch_cfg_model(k, c, r); }
 
 }  // namespace gofmm

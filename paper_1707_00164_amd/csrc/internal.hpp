@@ -103,6 +103,22 @@ struct HostPlan {
 struct DeviceState;  // defined by the evaluator
 void device_state_free(DeviceState* d);
 
+// Staging slots for batched launches on one stream (see eval.hip).
+struct BatchRing {
+  static constexpr int NS = 4;
+  struct Slot {
+    char* dev = nullptr;
+    char* host = nullptr;     // pinned
+    size_t cap = 0;
+    size_t err_off = 0;
+    void* ev = nullptr;       // hipEvent_t
+  };
+  Slot slot[NS];
+  int next = 0;
+  int last = -1;
+  ~BatchRing();
+};
+
 // ------------------------------------------------------------------ compression
 struct Compression {
   // parameters
@@ -163,3 +179,8 @@ uint16_t to_bf16(double x);
 double from_bf16(uint16_t h);
 
 }  // namespace gofmm
+
+// The opaque handle of the C ABI.
+struct gofmm_compression {
+  gofmm::Compression c;
+};

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgofmm.so")
 GRAM_L2, ANGLE = 0, 1
 FP32, BF16, BF16X3 = 0, 1, 2
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ECALLBACK", -3: "ENOTSPD", -4: "ENOMEM",
-          -5: "EHIP", -6: "EIO", -7: "ELIMIT"}
+          -5: "EHIP", -6: "EIO", -7: "ELIMIT", -8: "ETIMEDOUT"}
 KERNEL_KINDS = {"gaussian": 0, "imq": 1, "laplace_like": 2}
 
 SAMPLER = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_int64,
@@ -47,6 +47,15 @@ class GofmmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
         self.code = code
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("pending", C.c_int64),
+                ("inflight", C.c_int64), ("models", C.c_int64), ("admit_queue", C.c_int64),
+                ("batches", C.c_int64), ("columns", C.c_int64), ("packed", C.c_int64),
+                ("hbm_used", C.c_int64), ("hbm_budget", C.c_int64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+                ("max_ms", C.c_double), ("elapsed_ms", C.c_double)]
 
 
 _lib = None
@@ -77,6 +86,16 @@ SIGNATURES = [
     ("gofmm_stats", C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     ("gofmm_free", None, [C.c_void_p]),
     ("gofmm_last_error", C.c_char_p, []),
+    ("gofmm_server_create", C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
+    ("gofmm_server_add", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int32)]),
+    ("gofmm_server_remove", C.c_int, [C.c_void_p, C.c_int32]),
+    ("gofmm_server_submit", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64,
+                                      C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
+    ("gofmm_server_wait", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
+    ("gofmm_server_test", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    ("gofmm_server_stats", C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    ("gofmm_server_reset_stats", C.c_int, [C.c_void_p]),
+    ("gofmm_server_destroy", None, [C.c_void_p]),
     ("gofmm_kernel_create", C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_double,
                                       C.c_double, C.POINTER(C.c_void_p)]),
     ("gofmm_kernel_sample", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_int64,
@@ -286,3 +305,60 @@ def batched_status() -> int:
 
 def batched_spin_limit(polls: int):
     _check(lib().gofmm_batched_spin_limit(polls))
+
+
+class Server:
+    """Request loop keeping compressions resident (the library's serving loop)."""
+
+    def __init__(self, hbm_budget_bytes: int, streams: int = 2, max_batch: int = 16):
+        h = C.c_void_p()
+        _check(lib().gofmm_server_create(int(hbm_budget_bytes), streams, max_batch, C.byref(h)))
+        self.h = h
+        self.models = {}
+
+    def add(self, comp: Compression, r_max: int) -> int:
+        m = C.c_int32()
+        _check(lib().gofmm_server_add(self.h, comp.h, int(r_max), C.byref(m)))
+        self.models[m.value] = comp
+        return m.value
+
+    def remove(self, model: int):
+        _check(lib().gofmm_server_remove(self.h, model))
+        self.models.pop(model, None)
+
+    def submit(self, model: int, W, U) -> int:
+        """Enqueue U = K~ W; W and U (CUDA float32, rows contiguous) must stay alive."""
+        q = C.c_int64()
+        _check(lib().gofmm_server_submit(self.h, model, W.shape[1], _ptr(W), W.stride(0), _ptr(U),
+                                         U.stride(0), C.byref(q)))
+        return q.value
+
+    def wait(self, request: int, timeout_ms: int = 0) -> float:
+        """Latency (ms) of a finished request; GofmmError ETIMEDOUT after timeout_ms > 0."""
+        ms = C.c_double()
+        _check(lib().gofmm_server_wait(self.h, request, int(timeout_ms), C.byref(ms)))
+        return ms.value
+
+    def test(self, request: int):
+        done = C.c_int32()
+        ms = C.c_double()
+        _check(lib().gofmm_server_test(self.h, request, C.byref(done), C.byref(ms)))
+        return bool(done.value), ms.value
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check(lib().gofmm_server_stats(self.h, C.byref(st)))
+        return st
+
+    def reset_stats(self):
+        _check(lib().gofmm_server_reset_stats(self.h))
+
+    def close(self):
+        if self.h:
+            lib().gofmm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.gofmm_server_destroy(self.h)
+            self.h = None

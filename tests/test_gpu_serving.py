@@ -1,0 +1,172 @@
+"""Serving loop: resident compressions, admission by HBM footprint, continuous
+batching.  Every request's result must equal its standalone evaluate bit for
+bit, whatever it was batched or packed with."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import cuda_rhs, export_read, log, rel_err
+from oracle import evaluate, kernels
+
+pytestmark = pytest.mark.gpu
+
+MODELS = [  # (n, dim, kernel, h)
+    (1200, 3, "gaussian", 0.5),
+    (2500, 4, "laplace_like", 1.0),
+    (3300, 5, "imq", 0.4),
+    (5000, 3, "gaussian", 0.3),
+]
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1707_00164_amd as g
+    comps, Ks = [], []
+    for i, (n, d, kind, h) in enumerate(MODELS):
+        pts = np.random.default_rng(300 + i).random((n, d))
+        comps.append(g.Compression.compress(g.KernelSampler(pts, kind, h, 1e-2), leaf_size=256,
+                                            max_rank=96, tol=1e-5, kappa=16, budget=0.03, seed=i))
+        Ks.append(kernels.KernelMatrix(pts, kind, h, 1e-2))
+    return g, torch, comps, Ks
+
+
+def _requests(torch, comps, per_model=4, seed=0):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(per_model):
+        for i, c in enumerate(comps):
+            r = int(rng.integers(1, 40))
+            W = cuda_rhs(c.n, r, 1000 * i + 10 * k + seed)[1]
+            reqs.append((i, W))
+    return reqs
+
+
+def test_results_same_alone_and_in_mix(env):
+    g, torch, comps, Ks = env
+    log("case serving mix: 4 models x 4 requests, r in [1, 40)")
+    reqs = _requests(torch, comps)
+    alone = []
+    for i, W in reqs:
+        alone.append(comps[i].evaluate(W))
+    torch.cuda.synchronize()
+    alone = [a.cpu().numpy() for a in alone]
+    srv = g.Server(hbm_budget_bytes=8 << 30, streams=2, max_batch=8)
+    try:
+        ids = [srv.add(c, 64) for c in comps]
+        outs = [torch.full_like(W, float("nan")) for _, W in reqs]
+        torch.cuda.synchronize()
+        handles = [None] * len(reqs)
+
+        def producer():                      # arrivals spread over time, while batches run
+            for j, (i, W) in enumerate(reqs):
+                handles[j] = srv.submit(ids[i], W, outs[j])
+                time.sleep(0.0005 * (j % 3))
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        lat = [srv.wait(h, timeout_ms=60000) for h in handles]
+        st = srv.stats()
+        log(f"  completed {st.completed} failed {st.failed} batches {st.batches} packed {st.packed} "
+            f"p50 {st.p50_ms:.3f} ms p99 {st.p99_ms:.3f} ms")
+        assert st.completed == len(reqs) and st.failed == 0
+        assert st.p99_ms >= st.p50_ms > 0 and all(x > 0 for x in lat)
+        for j in range(len(reqs)):
+            assert np.array_equal(outs[j].cpu().numpy(), alone[j]), j
+        # and against the oracle for one request per model
+        for i in range(len(comps)):
+            j = i
+            ref = evaluate.tree_walk(export_read(comps[i]), Ks[i], reqs[j][1].cpu().numpy().astype(np.float64))
+            assert rel_err(outs[j].cpu().numpy(), ref) <= 1e-5
+    finally:
+        srv.close()
+
+
+def test_packing_several_requests_per_model(env):
+    g, torch, comps, Ks = env
+    log("case packing: 6 requests for one model submitted together")
+    c = comps[1]
+    Ws = [cuda_rhs(c.n, r, 50 + r)[1] for r in (3, 8, 1, 17, 5, 12)]
+    alone = [c.evaluate(W) for W in Ws]
+    torch.cuda.synchronize()
+    alone = [a.cpu().numpy() for a in alone]
+    srv = g.Server(hbm_budget_bytes=8 << 30, streams=1, max_batch=4)
+    try:
+        mid = srv.add(c, 64)
+        outs = [torch.empty_like(W) for W in Ws]
+        torch.cuda.synchronize()
+        hs = [srv.submit(mid, W, U) for W, U in zip(Ws, outs)]
+        for h in hs:
+            srv.wait(h, timeout_ms=60000)
+        st = srv.stats()
+        log(f"  batches {st.batches} packed {st.packed} columns {st.columns}")
+        assert st.columns == sum(W.shape[1] for W in Ws)
+        for U, a in zip(outs, alone):
+            assert np.array_equal(U.cpu().numpy(), a)
+    finally:
+        srv.close()
+
+
+def test_admission_waits_for_hbm(env):
+    g, torch, comps, Ks = env
+    log("case admission by footprint")
+    need = [c.footprint(32) + 2 * c.n * 32 * 4 for c in comps[:3]]
+    budget = need[0] + need[1] + need[2] - 1           # the third fits once either other one leaves
+    srv = g.Server(hbm_budget_bytes=budget, streams=2, max_batch=4)
+    try:
+        m = [srv.add(c, 32) for c in comps[:3]]
+        time.sleep(0.2)
+        st = srv.stats()
+        assert st.models == 2 and st.admit_queue == 1 and st.hbm_used <= budget
+        W = cuda_rhs(comps[2].n, 7, 3)[1]
+        U = torch.empty_like(W)
+        torch.cuda.synchronize()
+        h = srv.submit(m[2], W, U)
+        time.sleep(0.2)
+        done, _ = srv.test(h)
+        assert not done                                 # its model is not resident yet
+        srv.remove(m[0])                                # frees room: the third is admitted
+        srv.wait(h, timeout_ms=60000)
+        st = srv.stats()
+        assert st.models == 2 and st.admit_queue == 0 and st.hbm_used <= budget
+        out = U.cpu().numpy()
+        alone = comps[2].evaluate(W).cpu().numpy()
+        assert np.array_equal(out, alone)
+    finally:
+        srv.close()
+
+
+def test_wait_times_out_for_a_model_that_cannot_be_admitted(env):
+    g, torch, comps, Ks = env
+    need = [c.footprint(16) + 2 * c.n * 16 * 4 for c in comps[:2]]
+    srv = g.Server(hbm_budget_bytes=max(need) + 1, streams=1, max_batch=2)
+    try:
+        big = 0 if need[0] > need[1] else 1
+        m0 = srv.add(comps[big], 16)
+        m1 = srv.add(comps[1 - big], 16)                # waits for HBM behind the first
+        W = cuda_rhs(comps[1 - big].n, 3, 1)[1]
+        U = torch.empty_like(W)
+        torch.cuda.synchronize()
+        h = srv.submit(m1, W, U)
+        with pytest.raises(g.GofmmError) as e:
+            srv.wait(h, timeout_ms=300)
+        assert e.value.code == -8
+        srv.remove(m0)
+        srv.wait(h, timeout_ms=60000)
+        assert np.array_equal(U.cpu().numpy(), comps[1 - big].evaluate(W).cpu().numpy())
+    finally:
+        srv.close()
+
+
+def test_footprint_over_budget_rejected(env):
+    g, torch, comps, Ks = env
+    srv = g.Server(hbm_budget_bytes=1 << 20, streams=1, max_batch=2)
+    try:
+        with pytest.raises(g.GofmmError) as e:
+            srv.add(comps[3], 64)
+        assert e.value.code == -4
+    finally:
+        srv.close()
