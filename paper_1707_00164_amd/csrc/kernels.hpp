@@ -41,6 +41,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 32;
 constexpr int NT = 256;
@@ -60,6 +61,14 @@ struct KArgs {
   int r;
   int vec;              // rows of W, U, WS are 16-byte aligned
 };
+
+// Pointers into device memory as global-address-space pointers, so loads and
+// stores use the global (not generic flat) instructions even when the pointer
+// itself was read from memory (the batched launch).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned int u = __builtin_bit_cast(unsigned int, f);
@@ -83,9 +92,10 @@ struct Smem {
   int sOut[BM];
 };
 
-// One BM x BN output tile of task td (rows m0.., columns n0..).
-template <int PREC, int BM, int BN, int WM, int WN, bool ACC>
-__device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, int m0, int n0,
+// One BM x BN output tile of task td (rows m0.., columns n0..); acc adds the
+// product to the output instead of overwriting it.
+template <int PREC, int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, int m0, int n0, bool accumulate,
                                           Smem<PREC, BM, BN>& sm) {
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 32, TN = WTN / 32;
   static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "tile shape");
@@ -98,7 +108,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   E* sB = sm.sB;
   int* sOut = sm.sOut;
   const int tid = threadIdx.x;
-  const int* codes = a.rows + td.idx_off;
+  const auto codes = gmem(a.rows + td.idx_off);
   for (int i = tid; i < BM; i += NT) sOut[i] = (m0 + i < td.m) ? codes[td.lda + m0 + i] : ROW_ZERO;
 
   constexpr int EPU = F32 ? 4 : 8;                   // A elements per 16-byte unit
@@ -107,9 +117,9 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   // registers, so that LDS receives k-contiguous 16-byte vectors per column.
   constexpr int KS = 4;
   constexpr int BSUB = (BK / KS) * (BN / 4), BST = (BSUB + NT - 1) / NT;
-  uint4 ra[NPL][AUT];
+  u32x4 ra[NPL][AUT];
   f32x4 rb[BST][KS];
-  const E* Ab = reinterpret_cast<const E*>(a.A);
+  const auto Ab = gmem(reinterpret_cast<const E*>(a.A));
   // Row codes of B are fetched one slab ahead of the B rows they address, so
   // that the address of a B load never waits on a code load.
   int nc[BST][KS];
@@ -132,11 +142,11 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
         const int row = u / (BK / EPU), c = u % (BK / EPU);
         if (m0 + row < td.m) {
           const long long off = td.a_off + (long long)(m0 + row) * td.lda + k0 + c * EPU;
-          ra[0][t] = *reinterpret_cast<const uint4*>(Ab + off);
-          if constexpr (X3) ra[NPL - 1][t] = *reinterpret_cast<const uint4*>(Ab + a.plane + off);
+          ra[0][t] = *(const __attribute__((address_space(1))) u32x4*)(Ab + off);
+          if constexpr (X3) ra[NPL - 1][t] = *(const __attribute__((address_space(1))) u32x4*)(Ab + a.plane + off);
         } else {
 #pragma unroll
-          for (int p = 0; p < NPL; ++p) ra[p][t] = make_uint4(0, 0, 0, 0);
+          for (int p = 0; p < NPL; ++p) ra[p][t] = u32x4{0u, 0u, 0u, 0u};
         }
       }
     }
@@ -151,10 +161,10 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
           const int code = nc[t][e];
           f32x4 v = {0.f, 0.f, 0.f, 0.f};
           if (code != ROW_ZERO) {
-            const float* p = code >= 0 ? a.W + (long long)code * a.ldw
-                                       : a.WS + (long long)(-(code + 1)) * a.ldws;
+            const auto p = gmem(code >= 0 ? a.W + (long long)code * a.ldw
+                                          : a.WS + (long long)(-(code + 1)) * a.ldws);
             if (a.vec && col + 3 < a.r) {
-              v = *reinterpret_cast<const f32x4*>(p + col);
+              v = *(const __attribute__((address_space(1))) f32x4*)(p + col);
             } else {
               if (col < a.r) v[0] = p[col];
               if (col + 1 < a.r) v[1] = p[col + 1];
@@ -176,7 +186,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
         const int row = u / (BK / EPU), c = u % (BK / EPU);
 #pragma unroll
         for (int p = 0; p < NPL; ++p)
-          *reinterpret_cast<uint4*>(&sA[p * BM * LDK + row * LDK + c * EPU]) = ra[p][t];
+          *reinterpret_cast<u32x4*>(&sA[p * BM * LDK + row * LDK + c * EPU]) = ra[p][t];
       }
     }
 #pragma unroll
@@ -293,12 +303,12 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       const int row = wr * WTM + i * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
       if (m0 + row >= td.m) continue;
       const int code = sOut[row];
-      float* p = code >= 0 ? a.U + (long long)code * a.ldu : a.WS + (long long)(-(code + 1)) * a.ldws;
+      const auto p = gmem(code >= 0 ? a.U + (long long)code * a.ldu : a.WS + (long long)(-(code + 1)) * a.ldws);
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int col = n0 + wc * WTN + j * 32 + li;
         if (col < a.r) {
-          if constexpr (ACC) p[col] += acc[i][j][v];
+          if (accumulate) p[col] += acc[i][j][v];
           else p[col] = acc[i][j][v];
         }
       }
@@ -311,7 +321,7 @@ __device__ __forceinline__ void gemm_tiles(const KArgs& a) {
   const int2 it = a.items[blockIdx.x];
   if (it.x < 0) return;
   const TaskDesc td = a.tasks[it.x];
-  tile_body<PREC, BM, BN, WM, WN, ACC>(a, td, (it.y >> 16) * BM, (it.y & 0xffff) * BN, sm);
+  tile_body<PREC, BM, BN, WM, WN>(a, td, (it.y >> 16) * BM, (it.y & 0xffff) * BN, ACC, sm);
 }
 
 
@@ -430,8 +440,7 @@ __global__ __launch_bounds__(NT) void batched_tiles(BArgs b) {
       const TaskDesc td = in.tasks[__builtin_amdgcn_readfirstlane(it.task)];
       const int tile = __builtin_amdgcn_readfirstlane(it.tile);
       const int m0 = (tile >> 16) * BM, n0 = (tile & 0xffff) * BN;
-      if (b.stage_acc[stage]) tile_body<PREC, BM, BN, WM, WN, true>(a, td, m0, n0, sm);
-      else tile_body<PREC, BM, BN, WM, WN, false>(a, td, m0, n0, sm);
+      tile_body<PREC, BM, BN, WM, WN>(a, td, m0, n0, b.stage_acc[stage] != 0, sm);
     }
     last_stage = stage;
     __syncthreads();                      // every thread's stores issued, LDS free
