@@ -195,7 +195,8 @@ def form_large(args):
     rows = workloads.sample_rows(w.n, 64, w.seed)
     res = {}
     ref_rows = {}
-    forms = [("fp32", g.FP32, g.FP32), ("bf16", g.BF16, g.FP32), ("bf16x3", g.BF16X3, g.BF16X3)]
+    forms = [f for f in [("fp32", g.FP32, g.FP32), ("bf16", g.BF16, g.FP32), ("bf16x3", g.BF16X3, g.BF16X3)]
+             if f[0] in args.precisions]
     for r in args.r_list:
         W = torch.from_numpy(workloads.rhs(w.n, r, w.seed).astype(np.float32)).cuda()
         U = torch.empty_like(W)
@@ -322,6 +323,7 @@ def main():
     ap.add_argument("--hbm-gb", type=int, default=64)
     ap.add_argument("--max-n", type=int, default=262144)
     ap.add_argument("--r-list", type=int, nargs="+", default=[1024, 2048])
+    ap.add_argument("--precisions", nargs="+", default=["fp32", "bf16", "bf16x3"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU only; every box here has one "

@@ -273,7 +273,17 @@ static bool make_args(Compression& c, int li, int cfg, const EvalArgs& e, dev::K
   return true;
 }
 
+// GOFMM_TILE=<index> forces one tile shape for every launch (testing aid).
+static int forced_tile() {
+  const char* e = std::getenv("GOFMM_TILE");
+  if (!e || !*e) return -1;
+  const int v = std::atoi(e);
+  return (v >= 0 && v < kNumCfg) ? v : -1;
+}
+
 static int cfg_for(Compression& c, int li, i64 r) {
+  const int f = forced_tile();
+  if (f >= 0) return f;
   auto it = c.dev->tuned.find({li, r});
   return it != c.dev->tuned.end() ? it->second : choose_cfg(c, li, r);
 }
@@ -635,7 +645,8 @@ void device_evaluate_batched(int k, Compression* const* c, const i64* r, const f
   std::lock_guard<std::mutex> g(api_mutex());
   batch_prepare(k, c, r);
   auto it = batch_tuned().find(batch_key(k, c, r));
-  const int cfg = it != batch_tuned().end() ? it->second : batch_cfg_model(k, c, r);
+  int cfg = it != batch_tuned().end() ? it->second : batch_cfg_model(k, c, r);
+  if (forced_tile() >= 0) cfg = forced_tile();
   ring_launch(api_ring(), k, c, r, W, ldw, U, ldu, (hipStream_t)stream, cfg);
 }
 

@@ -448,10 +448,11 @@ __global__ __launch_bounds__(NT) void batched_tiles(BArgs b) {
 }
 
 typedef void (*BatchedFn)(BArgs);
-constexpr int kNumCfg = 6;
+constexpr int kNumCfg = 8;
 constexpr int kNumFamily = 5;   // n2s, s2s, s2n (accumulate), leaf, leaf accumulating
 struct Cfg { int bm, bn; };
-constexpr Cfg kCfgs[kNumCfg] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}, {128, 32}, {32, 128}};
+constexpr Cfg kCfgs[kNumCfg] = {{128, 128}, {128, 64}, {64, 128}, {64, 64},
+                                {128, 32}, {32, 128}, {256, 128}, {128, 256}};
 
 template <int PREC, int BM, int BN, int WM, int WN>
 void fill_family(KernelFn* row, BatchedFn* brow) {
@@ -472,6 +473,8 @@ void fill_table(KernelFn* table, BatchedFn* batched) {
   fill_family<PREC, 64, 64, 2, 2>(table + 3 * kNumFamily, batched + 3);
   fill_family<PREC, 128, 32, 4, 1>(table + 4 * kNumFamily, batched + 4);
   fill_family<PREC, 32, 128, 1, 4>(table + 5 * kNumFamily, batched + 5);
+  fill_family<PREC, 256, 128, 2, 2>(table + 6 * kNumFamily, batched + 6);
+  fill_family<PREC, 128, 256, 2, 2>(table + 7 * kNumFamily, batched + 7);
 }
 
 void kernels_f32(KernelFn* table, BatchedFn* batched);

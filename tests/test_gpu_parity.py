@@ -182,3 +182,31 @@ def test_mixed_near_fp32_far_bf16(torch):
     K = kernels.KernelMatrix(pts, w.kernel, w.h, w.shift)
     U, ref = _run(torch, comp, K, w.n, 20, w.seed)
     _check(U, ref, tol=TOL_X3_F, tol_elem=TOL_X3_E, what="x3 far / fp32 near")
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16x3", "bf16"])
+def test_every_tile_shape(torch, storage, monkeypatch):
+    """Each of the kernel's tile shapes, forced for every launch, on the ragged
+    FMM case (leaf sizes 93/94, ranks up to 64, r = 45)."""
+    import paper_1707_00164_amd as g
+    prec = {"fp32": g.FP32, "bf16x3": g.BF16X3, "bf16": g.BF16}[storage]
+    tol, tol_e = {"fp32": (TOL, TOL), "bf16x3": (TOL_X3_F, TOL_X3_E), "bf16": (2e-2, 1.0)}[storage]
+    rng = np.random.default_rng(4)
+    n = 3001
+    pts = rng.random((n, 3))
+    S = _sampler(pts, "gaussian", 0.3, 1e-3)
+    comp = g.Compression.compress(S, leaf_size=100, max_rank=64, tol=1e-6, kappa=16, budget=0.1, seed=5,
+                                  storage=prec, near_storage=prec)
+    K = kernels.KernelMatrix(pts, "gaussian", 0.3, 1e-3)
+    W64, Wd = cuda_rhs(n, 45, 77)
+    ref = evaluate.tree_walk(export_read(comp), K, Wd.cpu().numpy().astype(np.float64))
+    outs = []
+    for t in range(8):
+        monkeypatch.setenv("GOFMM_TILE", str(t))
+        U = comp.evaluate(Wd)
+        torch.cuda.synchronize()
+        log(f"case tile shape {t} storage {storage}")
+        outs.append(U.cpu().numpy())
+        _check(outs[-1], ref, tol=tol, tol_elem=tol_e, what=f"tile {t} {storage}")
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])          # fixed k order: identical whatever the tile shape
