@@ -305,6 +305,18 @@ def form_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def form_copy(args):
+    """A device-to-device copy of exactly 1 GiB (counter calibration: the
+    traffic counters of this copy should read 1 GiB fetched, 1 GiB written)."""
+    import torch
+    x = torch.ones(1 << 28, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"form": "copy", "bytes": 4 << 28, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,7 +326,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--rows", type=int, default=256, help="rows in the oracle sample")
-    ap.add_argument("--form", default="flat", choices=["flat", "batched", "serving", "large"],
+    ap.add_argument("--form", default="flat", choices=["flat", "batched", "serving", "large", "copy"],
                     help="flat: the N=65536 workload (default); batched: 48 compressions in one launch; "
                          "serving: request loop with p50/p99; large: N=262144 in three precisions")
     ap.add_argument("--instances", type=int, default=48)
@@ -339,7 +351,8 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     g.lib()
     if args.form != "flat":
-        {"batched": form_batched, "serving": form_serving, "large": form_large}[args.form](args)
+        {"batched": form_batched, "serving": form_serving, "large": form_large,
+         "copy": form_copy}[args.form](args)
         return
     w = workloads.clustered_gaussian()
     pts = workloads.points(w)
