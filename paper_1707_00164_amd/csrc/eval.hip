@@ -54,13 +54,18 @@ static int family_of(const LaunchDesc& l) {
   return l.accumulate ? 4 : 3;
 }
 
+// [vec][precision]: vec = 1 when every row of W, U and the workspace is
+// 16-byte aligned and r % 4 == 0
 struct Tables {
-  KernelFn k[3][kNumCfg * kNumFamily];
-  dev::BatchedFn b[3][kNumCfg];
+  KernelFn k[2][3][kNumCfg * kNumFamily];
+  dev::BatchedFn b[2][3][kNumCfg];
   Tables() {
-    dev::kernels_f32(k[PREC_F32], b[PREC_F32]);
-    dev::kernels_bf16(k[PREC_BF16], b[PREC_BF16]);
-    dev::kernels_x3(k[PREC_BF16X3], b[PREC_BF16X3]);
+    dev::kernels_f32_vec(k[1][PREC_F32], b[1][PREC_F32]);
+    dev::kernels_f32_any(k[0][PREC_F32], b[0][PREC_F32]);
+    dev::kernels_bf16_vec(k[1][PREC_BF16], b[1][PREC_BF16]);
+    dev::kernels_bf16_any(k[0][PREC_BF16], b[0][PREC_BF16]);
+    dev::kernels_x3_vec(k[1][PREC_BF16X3], b[1][PREC_BF16X3]);
+    dev::kernels_x3_any(k[0][PREC_BF16X3], b[0][PREC_BF16X3]);
   }
 };
 static const Tables& tables() {
@@ -68,8 +73,8 @@ static const Tables& tables() {
   return t;
 }
 
-static KernelFn kernel_for(const LaunchDesc& l, int cfg) {
-  return tables().k[l.prec][cfg * kNumFamily + family_of(l)];
+static KernelFn kernel_for(const LaunchDesc& l, int cfg, bool vec) {
+  return tables().k[vec ? 1 : 0][l.prec][cfg * kNumFamily + family_of(l)];
 }
 
 // ------------------------------------------------------------------ device state
@@ -268,7 +273,7 @@ static bool make_args(Compression& c, int li, int cfg, const EvalArgs& e, dev::K
   a.WS = d->ws;
   a.ldws = ws_cols_for(e.r);
   a.r = (int)e.r;
-  a.vec = ((uintptr_t)e.W % 16 == 0) && ((uintptr_t)e.U % 16 == 0) && e.ldw % 4 == 0 && e.ldu % 4 == 0;
+  a.vec = ((uintptr_t)e.W % 16 == 0) && ((uintptr_t)e.U % 16 == 0) && e.ldw % 4 == 0 && e.ldu % 4 == 0 && e.r % 4 == 0;
   grid = it.second;
   return true;
 }
@@ -296,7 +301,7 @@ static void launch_all(Compression& c, const EvalArgs& e) {
     dev::KArgs a;
     int grid = 0;
     if (!make_args(c, li, cfg, e, a, grid)) continue;
-    KernelFn fn = kernel_for(l, cfg);
+    KernelFn fn = kernel_for(l, cfg, a.vec != 0);
     if (d->profiling) {
       hipEvent_t ev[2];
       for (int q = 0; q < 2; ++q) {
@@ -350,7 +355,7 @@ void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
       LaunchDesc lo = c.plan.launches[li];
       if (lo.kind == 6) lo.kind = 1;
       lo.accumulate = 0;
-      KernelFn fn = kernel_for(lo, q);
+      KernelFn fn = kernel_for(lo, q, a.vec != 0);
       hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::NT), 0, st, a);
       HIP_OK(hipEventRecord(e0, st));
       for (int t = 0; t < reps; ++t) hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::NT), 0, st, a);
@@ -494,7 +499,7 @@ static int batch_grid_cap(int prec, int cfg) {
   if (it != cache.end()) return it->second;
   int per_cu = 0, cus = 0, devid = 0;
   HIP_OK(hipGetDevice(&devid));
-  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tables().b[prec][cfg], dev::NT, 0));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tables().b[1][prec][cfg], dev::NT, 0));
   HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
   const int cap = std::max(1, per_cu) * std::max(1, cus);
   cache[{prec, cfg}] = cap;
@@ -558,6 +563,7 @@ void ring_launch(BatchRing& ring, int k, Compression* const* c, const i64* r, co
     tab[2 * ns + q] = acc[q];
   }
   dev::BInst* in = reinterpret_cast<dev::BInst*>(h + o_inst);
+  bool all_vec = true;
   for (int i = 0; i < k; ++i) {
     DeviceState* d = c[i]->dev;
     in[i].tasks = d->tasks;
@@ -571,7 +577,8 @@ void ring_launch(BatchRing& ring, int k, Compression* const* c, const i64* r, co
     in[i].WS = d->ws;
     in[i].ldws = ws_cols_for(r[i]);
     in[i].r = (int)r[i];
-    in[i].vec = ((uintptr_t)W[i] % 16 == 0) && ((uintptr_t)U[i] % 16 == 0) && ldw[i] % 4 == 0 && ldu[i] % 4 == 0;
+    in[i].vec = ((uintptr_t)W[i] % 16 == 0) && ((uintptr_t)U[i] % 16 == 0) && ldw[i] % 4 == 0 && ldu[i] % 4 == 0 && r[i] % 4 == 0;
+    all_vec = all_vec && in[i].vec;
   }
   if (n_item) std::memcpy(h + o_item, items.data(), n_item);
   *reinterpret_cast<int*>(h + o_err) = 0;
@@ -590,7 +597,7 @@ void ring_launch(BatchRing& ring, int k, Compression* const* c, const i64* r, co
     a.error = a.done + ns + 1;
     a.spin_limit = spin_limit_ref();
     const int grid = std::max(1, std::min(a.n_items, batch_grid_cap(prec, cfg)));
-    hipLaunchKernelGGL(tables().b[prec][cfg], dim3(grid), dim3(dev::NT), 0, st, a);
+    hipLaunchKernelGGL(tables().b[all_vec ? 1 : 0][prec][cfg], dim3(grid), dim3(dev::NT), 0, st, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(h + o_err, dv + o_cnt + (size_t)(ns + 1) * sizeof(int), sizeof(int), hipMemcpyDeviceToHost, st));
   }

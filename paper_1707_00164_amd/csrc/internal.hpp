@@ -66,7 +66,8 @@ enum Prec { PREC_F32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
 // row rows[idx_off + t] of the right-hand-side space and row i of out is row
 // rows[idx_off + lda + i] of the output space (row codes below).
 struct TaskDesc {
-  i64 a_off;    // element offset of A (row-major, leading dim lda) in its buffer
+  i64 a_off;    // element offset of A in its buffer, in matrix-core fragment
+                // order (rows padded to 32, k to lda), see the packing
   i64 idx_off;  // offset into the row-code array
   i32 m, k, lda, node;
 };

@@ -9,11 +9,14 @@
 // A is a packed operator block (P, P^T, coupling K(b~, a~) or near K(b, a)),
 // B's rows are gathered by row code from the caller's W or from the skeleton
 // workspace, and out's rows are scattered the same way (the permutation is
-// folded into the codes).  Work item = one BM x BN output tile.  The k loop
-// stages a BM x 32 slab of A and a 32 x BN slab of B through LDS (B is
+// folded into the codes).  Work item = one BM x BN output tile.  FP32: the k
+// loop stages a BM x 32 slab of A and a 32 x BN slab of B through LDS (B is
 // transposed on the way in so both operands are read k-contiguous), with the
 // next slab's global loads in flight while the matrix cores work on the
-// current one.  Matrix-core instructions (64-wide waves, 4 waves per block):
+// current one.  BF16 forms: A is stored in matrix-core fragment order and read
+// by each wave straight into registers; only B goes through LDS, double
+// buffered in slabs of 64.  Matrix-core instructions (64-wide waves, 4 waves
+// per block):
 //
 //   FP32    v_mfma_f32_32x32x2_f32   (A, B in FP32)
 //   BF16    v_mfma_f32_32x32x16_bf16 (A stored BF16, B rounded to BF16)
@@ -39,11 +42,10 @@ namespace dev {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int BK = 32;
 constexpr int NT = 256;
 
 struct KArgs {
@@ -59,7 +61,7 @@ struct KArgs {
   float* WS;
   long long ldws;
   int r;
-  int vec;              // rows of W, U, WS are 16-byte aligned
+  int vec;              // rows of W, U, WS are 16-byte aligned and r % 4 == 0
 };
 
 // Pointers into device memory as global-address-space pointers, so loads and
@@ -70,31 +72,45 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
 
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned int u = __builtin_bit_cast(unsigned int, f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_val(unsigned short h) {
-  return __builtin_bit_cast(float, (unsigned int)h << 16);
-}
 
-// LDS of one block: A and B slabs (two planes each for split BF16) and the
-// output row codes of the tile.
+// LDS of one block: B only, double-buffered, one k slab per buffer (32 FP32 or
+// 64 BF16 values = 128 bytes per column).  Column c occupies 36 words (the
+// slab and 4 words of padding); its 16-byte chunk q sits at chunk position
+// q ^ ((c >> 4) & 3).  With this stride and swizzle both the fragment reads
+// (16 consecutive columns, one chunk) and the transposing writes (columns 4
+// apart, consecutive chunks) touch 16 distinct 4-bank groups.
 template <int PREC, int BM, int BN>
 struct Smem {
-  static constexpr bool F32 = PREC == PREC_F32;
   static constexpr int NPL = PREC == PREC_BF16X3 ? 2 : 1;
-  static constexpr int LDK = F32 ? BK + 4 : BK + 8;  // row stride (elements)
-  using E = typename std::conditional<F32, float, unsigned short>::type;
-  __attribute__((aligned(16))) E sA[NPL * BM * LDK];
-  __attribute__((aligned(16))) E sB[NPL * BN * LDK];
+  static constexpr int CW = 36;
+  __attribute__((aligned(16))) unsigned int sB[2][NPL][BN * CW];
   int sOut[BM];
 };
 
-// One BM x BN output tile of task td (rows m0.., columns n0..); acc adds the
-// product to the output instead of overwriting it.
-template <int PREC, int BM, int BN, int WM, int WN>
+__device__ __forceinline__ int swz(int c, int q) { return c * 36 + 4 * (q ^ ((c >> 4) & 3)); }
+
+// One BM x BN output tile of task td (rows m0.., columns n0..); accumulate adds
+// the product to the output instead of overwriting it.
+//
+// A is stored in matrix-core fragment order: chunks of 32 rows, one 16-byte
+// vector per lane (FP32: 4 values at k = 16h + 4s + q of a 32-slab, h the
+// half-wave, s the step; BF16: 8 values at k = 16s + 8h + e of a 64-slab).
+// Every wave loads its A fragments straight from global memory into
+// registers, one slab (four steps) ahead of use, with one coalesced 1 KiB load
+// per chunk and plane.  B rows are gathered two slabs ahead into registers
+// (their row codes three slabs ahead), transposed (and rounded or split to
+// BF16) into the LDS buffer that is not being read while the matrix cores
+// work on the current slab, and read back as fragments one step ahead: one
+// barrier per slab.  The k loop has no branch but the loop itself, and a
+// scheduling fence per step keeps each step's loads, conversions and LDS
+// traffic interleaved with its own matrix-core work.
+//
+// Per step and (row block, column block): FP32 four v_mfma_f32_32x32x2_f32
+// (the two half-waves feed k 16h + 4s + q, q = 0..3); BF16 one
+// v_mfma_f32_32x32x16_bf16; split BF16 three (lo*hi, hi*lo, hi*hi).  The k
+// order of the products is the same for every tile shape, so every shape
+// gives the same bits.
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
 __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, int m0, int n0, bool accumulate,
                                           Smem<PREC, BM, BN>& sm) {
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 32, TN = WTN / 32;
@@ -102,121 +118,131 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   constexpr bool F32 = PREC == PREC_F32;
   constexpr bool X3 = PREC == PREC_BF16X3;
   constexpr int NPL = X3 ? 2 : 1;                    // planes per operand
-  constexpr int LDK = Smem<PREC, BM, BN>::LDK;
-  using E = typename Smem<PREC, BM, BN>::E;
-  E* sA = sm.sA;
-  E* sB = sm.sB;
-  int* sOut = sm.sOut;
-  const int tid = threadIdx.x;
-  const auto codes = gmem(a.rows + td.idx_off);
-  for (int i = tid; i < BM; i += NT) sOut[i] = (m0 + i < td.m) ? codes[td.lda + m0 + i] : ROW_ZERO;
-
+  constexpr int KSLAB = F32 ? 32 : 64;               // k per slab
+  constexpr int NS = 4;                              // steps per slab
   constexpr int EPU = F32 ? 4 : 8;                   // A elements per 16-byte unit
-  constexpr int AU = BM * BK / EPU, AUT = (AU + NT - 1) / NT;
-  // B is loaded in sub-blocks of KS rows x 4 columns and transposed in
-  // registers, so that LDS receives k-contiguous 16-byte vectors per column.
-  constexpr int KS = 4;
-  constexpr int BSUB = (BK / KS) * (BN / 4), BST = (BSUB + NT - 1) / NT;
-  u32x4 ra[NPL][AUT];
-  f32x4 rb[BST][KS];
-  const auto Ab = gmem(reinterpret_cast<const E*>(a.A));
-  // Row codes of B are fetched one slab ahead of the B rows they address, so
-  // that the address of a B load never waits on a code load.
-  int nc[BST][KS];
+  constexpr int SBR = F32 ? 4 : 8;                   // B rows per sub-block (one 16-byte LDS chunk)
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, li = lane & 31, lh = lane >> 5;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wid / WN, wc = wid % WN;
+  const auto codes = gmem(a.rows + td.idx_off);
+  for (int i = tid; i < BM; i += NT) sm.sOut[i] = (m0 + i < td.m) ? codes[td.lda + m0 + i] : ROW_ZERO;
+
+  // A: ring of one slab of fragments per row block and plane.  Row blocks past
+  // the stored ones and steps past the end read chunk 0 of the block (always
+  // present); those products reach only rows that are never stored, or are
+  // never issued.
+  const int kch = td.lda / (KSLAB / NS);              // chunks per row block
+  const int nrb = (td.m + 31) >> 5;                   // row blocks stored
+  const int rb0 = (m0 + wr * WTM) >> 5;
+  const auto Ab = gmem(reinterpret_cast<const u32x4*>(a.A));
+  const long long abase = td.a_off / EPU;            // in 16-byte units
+  const long long aplane = a.plane / EPU;
+  u32x4 ra[NS][NPL][TM];
+  auto aload = [&](int slot, int g) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const bool ok = rb0 + i < nrb && g < kch;
+      const long long u = abase + (ok ? ((long long)(rb0 + i) * kch + g) * 64 : 0) + lane;
+      ra[slot][0][i] = Ab[u];
+      if constexpr (X3) ra[slot][1][i] = Ab[aplane + u];
+    }
+  };
+
+  // B: sub-blocks of SBR rows x 4 columns per thread and slab.  Codes of slabs
+  // past the end are clamped to the last k of the block: the rows they fetch
+  // only reach LDS buffers that are never read again.
+  constexpr int BSUB = (KSLAB / SBR) * (BN / 4), BST = (BSUB + NT - 1) / NT;
+  int nc[BST][SBR];
+  f32x4 rbv[BST][SBR];
   auto cload = [&](int k0) {
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
-      const int sub = tid + t * NT;
-      const int kq = sub / (BN / 4);
+      const int kq = (tid + t * NT) / (BN / 4);
 #pragma unroll
-      for (int e = 0; e < KS; ++e)
-        nc[t][e] = (sub < BSUB && k0 < td.lda) ? codes[k0 + kq * KS + e] : ROW_ZERO;
+      for (int e = 0; e < SBR; ++e) nc[t][e] = codes[min(k0 + kq * SBR + e, td.lda - 1)];
     }
   };
-
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int t = 0; t < AUT; ++t) {
-      const int u = tid + t * NT;
-      if (u < AU) {
-        const int row = u / (BK / EPU), c = u % (BK / EPU);
-        if (m0 + row < td.m) {
-          const long long off = td.a_off + (long long)(m0 + row) * td.lda + k0 + c * EPU;
-          ra[0][t] = *(const __attribute__((address_space(1))) u32x4*)(Ab + off);
-          if constexpr (X3) ra[NPL - 1][t] = *(const __attribute__((address_space(1))) u32x4*)(Ab + a.plane + off);
-        } else {
-#pragma unroll
-          for (int p = 0; p < NPL; ++p) ra[p][t] = u32x4{0u, 0u, 0u, 0u};
-        }
-      }
-    }
+  const auto Wg = gmem(a.W);
+  const auto WSg = gmem(a.WS);
+  // Every load is issued unconditionally and its value is left untouched until
+  // the slab is stored to LDS a slab later, where a bit mask zeroes what must
+  // read as zero (rows coded ROW_ZERO, columns past r): nothing waits for a B
+  // load early and the k loop stays free of branches.
+  unsigned int zmask[BST];                            // bit 4e + q: element (e, q) reads as 0
+  auto bload = [&]() {
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
       const int sub = tid + t * NT;
-      if (sub < BSUB) {
-        const int cq = sub % (BN / 4), kq = sub / (BN / 4);
-        const int col = n0 + 4 * cq;
+      const int col = n0 + 4 * (sub % (BN / 4));
+      const auto rowp = [&](int e, bool& zr) {
+        const int code = nc[t][e];
+        zr = code == ROW_ZERO;
+        const bool inw = code >= 0;
+        const long long idx = inw ? code : -(code + 1);
+        const long long ld = inw ? a.ldw : a.ldws;
+        return (inw ? Wg : WSg) + (zr ? 0 : idx * ld);
+      };
+      unsigned int zm = 0;
+      if constexpr (VEC) {                            // rows 16-byte aligned, r % 4 == 0
+        const bool zc = col >= a.r;
 #pragma unroll
-        for (int e = 0; e < KS; ++e) {
-          const int code = nc[t][e];
-          f32x4 v = {0.f, 0.f, 0.f, 0.f};
-          if (code != ROW_ZERO) {
-            const auto p = gmem(code >= 0 ? a.W + (long long)code * a.ldw
-                                          : a.WS + (long long)(-(code + 1)) * a.ldws);
-            if (a.vec && col + 3 < a.r) {
-              v = *(const __attribute__((address_space(1))) f32x4*)(p + col);
-            } else {
-              if (col < a.r) v[0] = p[col];
-              if (col + 1 < a.r) v[1] = p[col + 1];
-              if (col + 2 < a.r) v[2] = p[col + 2];
-              if (col + 3 < a.r) v[3] = p[col + 3];
-            }
+        for (int e = 0; e < SBR; ++e) {
+          bool zr;
+          const auto p = rowp(e, zr);
+          const bool z = zr || zc;
+          rbv[t][e] = *(const __attribute__((address_space(1))) f32x4*)(p + (z ? 0 : col));
+          zm |= z ? 0xfu << (4 * e) : 0u;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < SBR; ++e) {
+          bool zr;
+          const auto p = rowp(e, zr);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const bool z = zr || col + q >= a.r;
+            rbv[t][e][q] = p[z ? 0 : col + q];
+            zm |= z ? 1u << (4 * e + q) : 0u;
           }
-          rb[t][e] = v;
         }
       }
+      zmask[t] = zm;
     }
   };
-
-  auto lstore = [&]() {
-#pragma unroll
-    for (int t = 0; t < AUT; ++t) {
-      const int u = tid + t * NT;
-      if (u < AU) {
-        const int row = u / (BK / EPU), c = u % (BK / EPU);
-#pragma unroll
-        for (int p = 0; p < NPL; ++p)
-          *reinterpret_cast<u32x4*>(&sA[p * BM * LDK + row * LDK + c * EPU]) = ra[p][t];
-      }
-    }
+  auto bval = [&](int t, int e, int j) { return (zmask[t] >> (4 * e + j)) & 1u ? 0.f : rbv[t][e][j]; };
+  auto bstore = [&](int buf) {
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
       const int sub = tid + t * NT;
-      if (sub < BSUB) {
+      if (BSUB % NT == 0 || sub < BSUB) {
         const int cq = sub % (BN / 4), kq = sub / (BN / 4);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int idx = (4 * cq + j) * LDK + kq * KS;
+          const int w = swz(4 * cq + j, kq);
           if constexpr (F32) {
-            f32x4 v = {rb[t][0][j], rb[t][1][j], rb[t][2][j], rb[t][3][j]};
-            *reinterpret_cast<f32x4*>(&sB[idx]) = v;
+            const f32x4 v = {bval(t, 0, j), bval(t, 1, j), bval(t, 2, j), bval(t, 3, j)};
+            *reinterpret_cast<f32x4*>(&sm.sB[buf][0][w]) = v;
           } else {
-            u16x4 hi, lo;
+            u32x4 hi, lo;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              hi[e] = bf16_rne(rb[t][e][j]);
-              if constexpr (X3) lo[e] = bf16_rne(rb[t][e][j] - bf16_val(hi[e]));
+              const f32x2 x = {bval(t, 2 * e, j), bval(t, 2 * e + 1, j)};
+              const bf16x2 h = __builtin_convertvector(x, bf16x2);
+              hi[e] = __builtin_bit_cast(unsigned int, h);
+              if constexpr (X3) {
+                const f32x2 r = x - __builtin_convertvector(h, f32x2);
+                lo[e] = __builtin_bit_cast(unsigned int, __builtin_convertvector(r, bf16x2));
+              }
             }
-            *reinterpret_cast<u16x4*>(&sB[idx]) = hi;
-            if constexpr (X3) *reinterpret_cast<u16x4*>(&sB[BN * LDK + idx]) = lo;
+            *reinterpret_cast<u32x4*>(&sm.sB[buf][0][w]) = hi;
+            if constexpr (X3) *reinterpret_cast<u32x4*>(&sm.sB[buf][NPL - 1][w]) = lo;
           }
         }
       }
     }
   };
 
-  const int lane = tid & 63, li = lane & 31, lh = lane >> 5;
-  const int wid = tid >> 6, wr = wid / WN, wc = wid % WN;
   f32x16 acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -225,74 +251,84 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  auto compute = [&]() {
-    if constexpr (F32) {
-      // lane (li, lh) feeds k = lh * 16 + 4u + q: the two halves of the wave
-      // cover k 0..15 and 16..31 of the slab, matching A and B.
+  u32x4 bfr[2][NPL][TN];
+  auto bread = [&](int slot, int buf, int s) {
+    const int q = F32 ? 4 * lh + s : 2 * s + lh;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        f32x4 av[TM], bv[TN];
+    for (int j = 0; j < TN; ++j) {
+      const int w = swz(wc * WTN + j * 32 + li, q);
+#pragma unroll
+      for (int p = 0; p < NPL; ++p) bfr[slot][p][j] = *reinterpret_cast<const u32x4*>(&sm.sB[buf][p][w]);
+    }
+  };
+  auto mfma_step = [&](int s) {
+    const int bs = s & 1;
+    if constexpr (F32) {
+      // (whole vectors are reinterpreted before indexing: a bit cast of a
+      // single vector element reads element 0 with this compiler)
+      f32x4 av[TM], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) av[i] = __builtin_bit_cast(f32x4, ra[s][0][i]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bv[j] = __builtin_bit_cast(f32x4, bfr[bs][0][j]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
-          av[i] = *reinterpret_cast<const f32x4*>(&sA[(wr * WTM + i * 32 + li) * LDK + lh * 16 + 4 * u]);
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-          bv[j] = *reinterpret_cast<const f32x4*>(&sB[(wc * WTN + j * 32 + li) * LDK + lh * 16 + 4 * u]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][q], bv[j][q], acc[i][j], 0, 0, 0);
-      }
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][q], bv[j][q], acc[i][j], 0, 0, 0);
     } else {
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        bf16x8 ah[TM], bh[TN], al[TM], bl[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          const int o = (wr * WTM + i * 32 + li) * LDK + 16 * s + 8 * lh;
-          ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sA[o]));
-          if constexpr (X3) al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sA[BM * LDK + o]));
-        }
+      for (int i = 0; i < TM; ++i) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, ra[s][0][i]);
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          const int o = (wc * WTN + j * 32 + li) * LDK + 16 * s + 8 * lh;
-          bh[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sB[o]));
-          if constexpr (X3) bl[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sB[BN * LDK + o]));
-        }
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            if constexpr (X3) {
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-            }
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          const bf16x8 bh = __builtin_bit_cast(bf16x8, bfr[bs][0][j]);
+          if constexpr (X3) {
+            const bf16x8 al = __builtin_bit_cast(bf16x8, ra[s][NPL - 1][i]);
+            const bf16x8 bl = __builtin_bit_cast(bf16x8, bfr[bs][NPL - 1][j]);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[i][j], 0, 0, 0);
           }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[i][j], 0, 0, 0);
+        }
       }
     }
   };
 
-  const int nk = td.lda / BK;
-  if (nk > 0) {
+  const int ns = td.lda / KSLAB;
+  if (ns > 0) {
     cload(0);
-    gload(0);
-    cload(BK);
-  }
-  for (int kt = 0; kt < nk; ++kt) {
-    __syncthreads();
-    lstore();
-    __syncthreads();
-    if (kt + 1 < nk) {
-      gload((kt + 1) * BK);
-      cload((kt + 2) * BK);
-    }
-    compute();
+    bload();
+    cload(KSLAB);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) aload(s, s);
+    bstore(0);
+    bload();
+    cload(2 * KSLAB);
   }
   __syncthreads();
+  for (int kt = 0; kt < ns; ++kt) {
+    const int buf = kt & 1;
+    bread(0, buf, 0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (s + 1 < NS) bread((s + 1) & 1, buf, s + 1);
+      mfma_step(s);
+      aload(s, (kt + 1) * NS + s);
+      // slab kt + 1 into the other buffer (no wave reads it before the
+      // barrier below), then the B rows of slab kt + 2 and the codes of
+      // slab kt + 3; past the last slab these move data that nobody reads
+      if (s == 0) bstore(buf ^ 1);
+      if (s == 1) {
+        bload();
+        cload((kt + 3) * KSLAB);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+  }
 
   // epilogue: accumulator (i, j, v) of lane (li, lh) is row 8(v/4) + 4 lh + v%4,
   // column li of the 32 x 32 block
@@ -302,7 +338,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
     for (int v = 0; v < 16; ++v) {
       const int row = wr * WTM + i * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
       if (m0 + row >= td.m) continue;
-      const int code = sOut[row];
+      const int code = sm.sOut[row];
       const auto p = gmem(code >= 0 ? a.U + (long long)code * a.ldu : a.WS + (long long)(-(code + 1)) * a.ldws);
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
@@ -315,26 +351,28 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
     }
 }
 
-template <int PREC, int BM, int BN, int WM, int WN, bool ACC>
+// VEC: every W, U and workspace row is 16-byte aligned and r % 4 == 0 (B rows
+// are then loaded as 16-byte vectors)
+template <int PREC, int BM, int BN, int WM, int WN, bool ACC, bool VEC>
 __device__ __forceinline__ void gemm_tiles(const KArgs& a) {
   __shared__ Smem<PREC, BM, BN> sm;
   const int2 it = a.items[blockIdx.x];
   if (it.x < 0) return;
   const TaskDesc td = a.tasks[it.x];
-  tile_body<PREC, BM, BN, WM, WN>(a, td, (it.y >> 16) * BM, (it.y & 0xffff) * BN, ACC, sm);
+  tile_body<PREC, BM, BN, WM, WN, VEC>(a, td, (it.y >> 16) * BM, (it.y & 0xffff) * BN, ACC, sm);
 }
 
 
 // Entry points with the same body, so that profiles separate the upward pass,
 // the far field, the downward pass and the leaf output.
-template <int PREC, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(NT) void n2s_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false>(a); }
-template <int PREC, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(NT) void s2s_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false>(a); }
-template <int PREC, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(NT) void s2n_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, true>(a); }
-template <int PREC, int BM, int BN, int WM, int WN, bool ACC>
-__global__ __launch_bounds__(NT) void leaf_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, ACC>(a); }
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
+__global__ __launch_bounds__(NT) void n2s_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false, VEC>(a); }
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
+__global__ __launch_bounds__(NT) void s2s_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false, VEC>(a); }
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
+__global__ __launch_bounds__(NT) void s2n_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, true, VEC>(a); }
+template <int PREC, int BM, int BN, int WM, int WN, bool ACC, bool VEC>
+__global__ __launch_bounds__(NT) void leaf_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, ACC, VEC>(a); }
 
 typedef void (*KernelFn)(KArgs);
 
@@ -377,7 +415,7 @@ struct BArgs {
   long long spin_limit;
 };
 
-template <int PREC, int BM, int BN, int WM, int WN>
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
 __global__ __launch_bounds__(NT) void batched_tiles(BArgs b) {
   __shared__ Smem<PREC, BM, BN> sm;
   __shared__ int s_item;
@@ -440,7 +478,7 @@ __global__ __launch_bounds__(NT) void batched_tiles(BArgs b) {
       const TaskDesc td = in.tasks[__builtin_amdgcn_readfirstlane(it.task)];
       const int tile = __builtin_amdgcn_readfirstlane(it.tile);
       const int m0 = (tile >> 16) * BM, n0 = (tile & 0xffff) * BN;
-      tile_body<PREC, BM, BN, WM, WN>(a, td, m0, n0, b.stage_acc[stage] != 0, sm);
+      tile_body<PREC, BM, BN, WM, WN, VEC>(a, td, m0, n0, b.stage_acc[stage] != 0, sm);
     }
     last_stage = stage;
     __syncthreads();                      // every thread's stores issued, LDS free
@@ -454,32 +492,36 @@ struct Cfg { int bm, bn; };
 constexpr Cfg kCfgs[kNumCfg] = {{128, 128}, {128, 64}, {64, 128}, {64, 64},
                                 {128, 32}, {32, 128}, {256, 128}, {128, 256}};
 
-template <int PREC, int BM, int BN, int WM, int WN>
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
 void fill_family(KernelFn* row, BatchedFn* brow) {
-  *brow = batched_tiles<PREC, BM, BN, WM, WN>;
-  row[0] = n2s_tiles<PREC, BM, BN, WM, WN>;
-  row[1] = s2s_tiles<PREC, BM, BN, WM, WN>;
-  row[2] = s2n_tiles<PREC, BM, BN, WM, WN>;
-  row[3] = leaf_tiles<PREC, BM, BN, WM, WN, false>;
-  row[4] = leaf_tiles<PREC, BM, BN, WM, WN, true>;
+  *brow = batched_tiles<PREC, BM, BN, WM, WN, VEC>;
+  row[0] = n2s_tiles<PREC, BM, BN, WM, WN, VEC>;
+  row[1] = s2s_tiles<PREC, BM, BN, WM, WN, VEC>;
+  row[2] = s2n_tiles<PREC, BM, BN, WM, WN, VEC>;
+  row[3] = leaf_tiles<PREC, BM, BN, WM, WN, false, VEC>;
+  row[4] = leaf_tiles<PREC, BM, BN, WM, WN, true, VEC>;
 }
 
 // table[cfg * kNumFamily + family], batched[cfg]
-template <int PREC>
+template <int PREC, bool VEC>
 void fill_table(KernelFn* table, BatchedFn* batched) {
-  fill_family<PREC, 128, 128, 2, 2>(table + 0 * kNumFamily, batched + 0);
-  fill_family<PREC, 128, 64, 2, 2>(table + 1 * kNumFamily, batched + 1);
-  fill_family<PREC, 64, 128, 2, 2>(table + 2 * kNumFamily, batched + 2);
-  fill_family<PREC, 64, 64, 2, 2>(table + 3 * kNumFamily, batched + 3);
-  fill_family<PREC, 128, 32, 4, 1>(table + 4 * kNumFamily, batched + 4);
-  fill_family<PREC, 32, 128, 1, 4>(table + 5 * kNumFamily, batched + 5);
-  fill_family<PREC, 256, 128, 2, 2>(table + 6 * kNumFamily, batched + 6);
-  fill_family<PREC, 128, 256, 2, 2>(table + 7 * kNumFamily, batched + 7);
+  fill_family<PREC, 128, 128, 2, 2, VEC>(table + 0 * kNumFamily, batched + 0);
+  fill_family<PREC, 128, 64, 2, 2, VEC>(table + 1 * kNumFamily, batched + 1);
+  fill_family<PREC, 64, 128, 2, 2, VEC>(table + 2 * kNumFamily, batched + 2);
+  fill_family<PREC, 64, 64, 2, 2, VEC>(table + 3 * kNumFamily, batched + 3);
+  fill_family<PREC, 128, 32, 4, 1, VEC>(table + 4 * kNumFamily, batched + 4);
+  fill_family<PREC, 32, 128, 1, 4, VEC>(table + 5 * kNumFamily, batched + 5);
+  fill_family<PREC, 256, 128, 4, 1, VEC>(table + 6 * kNumFamily, batched + 6);
+  fill_family<PREC, 128, 256, 2, 2, VEC>(table + 7 * kNumFamily, batched + 7);
 }
 
-void kernels_f32(KernelFn* table, BatchedFn* batched);
-void kernels_bf16(KernelFn* table, BatchedFn* batched);
-void kernels_x3(KernelFn* table, BatchedFn* batched);
+// One translation unit per (precision, row alignment).
+void kernels_f32_vec(KernelFn* table, BatchedFn* batched);
+void kernels_f32_any(KernelFn* table, BatchedFn* batched);
+void kernels_bf16_vec(KernelFn* table, BatchedFn* batched);
+void kernels_bf16_any(KernelFn* table, BatchedFn* batched);
+void kernels_x3_vec(KernelFn* table, BatchedFn* batched);
+void kernels_x3_any(KernelFn* table, BatchedFn* batched);
 
 }  // namespace dev
 }  // namespace gofmm

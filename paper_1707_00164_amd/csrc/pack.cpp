@@ -1,7 +1,8 @@
 // Device operator layout: every step of the evaluation as gather-GEMM tasks.
 //
 // Each task computes out[m x r] = A[m x k] * B[k x r] (or +=), where A is a
-// dense block stored row-major in the operator buffer of its precision and
+// dense block in the operator buffer of its precision, in matrix-core fragment
+// order, and
 // the rows of B and of out are addressed through a row-code list (caller's W
 // or U rows through the permutation, or rows of the skeleton workspace).  The
 // steps of Alg. "Evaluate" (Sec. 2.2, Table 2) become:
@@ -29,9 +30,25 @@ namespace gofmm {
 
 namespace {
 
-constexpr i64 KALIGN = 32;   // k padding of every A block (the kernels' k tile)
-
+// k padding of A blocks (the kernels' k slab: 32 FP32 or 64 BF16 values);
+// rows are padded to 32.
 i64 round_up(i64 x, i64 a) { return (x + a - 1) / a * a; }
+i64 kalign(int prec) { return prec == PREC_F32 ? 32 : 64; }
+i64 rows_stored(i64 m) { return round_up(m, 32); }
+
+// Fragment order: A is cut into chunks of 32 rows, ordered by row block, then
+// k; inside a chunk, lane L = 32 h + i' of a 64-wide wave holds one 16-byte
+// vector of row i', exactly its A operand for one step of the kernel.
+//  FP32 (chunk = 8 k): k = 32 slab + 16 h + 4 s + q, chunk s of the slab,
+//                      element q of the vector (four 32x32x2 steps).
+//  BF16 (chunk = 16 k): k = 16 c + 8 h + e, element e (one 32x32x16 step).
+inline i64 frag_pos_f32(i64 i, i64 j, i64 lda) {
+  const i64 chunk = (i >> 5) * (lda >> 3) + ((j >> 5) << 2) + ((j >> 2) & 3);
+  return chunk * 256 + ((((j >> 4) & 1) << 5) + (i & 31)) * 4 + (j & 3);
+}
+inline i64 frag_pos_b16(i64 i, i64 j, i64 lda) {
+  return ((i >> 5) * (lda >> 4) + (j >> 4)) * 512 + ((((j >> 3) & 1) << 5) + (i & 31)) * 8 + (j & 7);
+}
 int elem_bytes(int prec) { return prec == PREC_BF16 ? 2 : 4; }
 
 // One part of a task's A: either a P-based block or a kernel block.
@@ -216,7 +233,7 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
     i64 k = 0;
     for (auto& p : d.parts) k += p.width;
     if ((i64)d.brow.size() != k || (i64)d.orow.size() != d.m) fail(GOFMM_EINVAL, "internal: task shape");
-    const i64 lda = round_up(k, KALIGN);
+    const i64 lda = round_up(k, kalign(d.prec));
     TaskDesc& td = pl.tasks[t];
     td.m = (i32)d.m;
     td.k = (i32)k;
@@ -224,7 +241,7 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
     td.node = 0;
     td.a_off = off[d.prec];
     td.idx_off = roff;
-    off[d.prec] += round_up(d.m * lda, KALIGN);
+    off[d.prec] += rows_stored(d.m) * lda;
     roff += lda + d.m;
   }
   pl.rows.assign(roff, ROW_ZERO);
@@ -292,11 +309,11 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
       if (d.prec == PREC_F32) {
         float* dst = &pl.a_f32[td.a_off];
         for (i64 i = 0; i < m; ++i)
-          for (i64 j = 0; j < k; ++j) dst[i * lda + j] = (float)A[i * k + j];
+          for (i64 j = 0; j < k; ++j) dst[frag_pos_f32(i, j, lda)] = (float)A[i * k + j];
       } else if (d.prec == PREC_BF16) {
         uint16_t* dst = &pl.a_b16[td.a_off];
         for (i64 i = 0; i < m; ++i)
-          for (i64 j = 0; j < k; ++j) dst[i * lda + j] = to_bf16(A[i * k + j]);
+          for (i64 j = 0; j < k; ++j) dst[frag_pos_b16(i, j, lda)] = to_bf16(A[i * k + j]);
       } else {
         uint16_t* hi = &pl.a_x3hi[td.a_off];
         uint16_t* lo = &pl.a_x3lo[td.a_off];
@@ -304,8 +321,8 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
           for (i64 j = 0; j < k; ++j) {
             const double x = A[i * k + j];
             const uint16_t h = to_bf16(x);
-            hi[i * lda + j] = h;
-            lo[i * lda + j] = to_bf16(x - from_bf16(h));
+            hi[frag_pos_b16(i, j, lda)] = h;
+            lo[frag_pos_b16(i, j, lda)] = to_bf16(x - from_bf16(h));
           }
       }
     } catch (const Error& e) {
