@@ -35,48 +35,68 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_steps(comp, W, U, steps, warmup, torch, profile=False):
+def time_steps(comp, W, U, steps, warmup, torch):
+    """Per-launch shares from an untimed profiled pass, then `steps` timed
+    evaluates with HIP events around the dominant launch only (two events per
+    step, on the evaluation stream).  Returns (seconds per step, launch index,
+    its average ms in the timed region, shares)."""
     for _ in range(warmup):
         comp.evaluate(W, U)
     torch.cuda.synchronize()
-    if profile:
-        comp.profile(True)
-        comp.profile_read()
+    comp.profile(True)
+    comp.profile_read()
+    for _ in range(3):
+        comp.evaluate(W, U)
+    ms, calls = comp.profile_read()
+    comp.profile(False)
+    names = [l[0] for l in comp.launches()]
+    share = {names[k]: round(ms[k] / max(sum(ms), 1e-30), 4) for k in range(len(ms))}
+    dom = max(range(len(ms)), key=lambda k: ms[k])
+    comp.profile(True, launch=dom)
+    comp.profile_read()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         comp.evaluate(W, U)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = None
-    if profile:
-        prof = comp.profile_read()
-        comp.profile(False)
-    return (t1 - t0) / steps, prof
+    ms, calls = comp.profile_read()
+    comp.profile(False)
+    return (t1 - t0) / steps, dom, ms[dom] / max(calls[dom], 1), share
 
 
-def roofline(comp, prof, r, steps, dtype):
-    ms, calls = prof
-    launches = comp.launches()
-    i = max(range(len(ms)), key=lambda k: ms[k])
-    name, fl, byts = launches[i]
-    avg_s = ms[i] / max(calls[i], 1) / 1e3
+# Peak of a precision form in algorithmic TFLOP/s: split BF16 issues three BF16
+# matrix-core products per FP32-equivalent product.
+FORM_PEAK = {"f32": ("f32", 1.0), "bf16": ("bf16", 1.0), "bf16x3": ("bf16", 3.0)}
+
+
+def roofline(comp, dom, dom_ms, share, r, form, near_form=None):
+    """Roofline of the dominant launch; `near_form` is the precision form of
+    the near-field launch (l2l) when it differs from the rest."""
+    name, fl, byts = comp.launches()[dom]
+    if name == "l2l" and near_form is not None:
+        form = near_form
+    avg_s = dom_ms / 1e3
     achieved = fl * r / avg_s / 1e12
-    peak = PEAK_TFLOPS[dtype]
+    base, products = FORM_PEAK[form]
+    peak = round(PEAK_TFLOPS[base] / products, 1)
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
         try:
             t = json.load(open(tfile))
-            if t.get("launch") == name and t.get("fingerprint") == _fingerprint():
+            if t.get("launch") == name and t.get("form", "f32") == form and t.get("fingerprint") == _fingerprint():
                 traffic = t.get("bytes_per_launch")
         except Exception:
             traffic = None
-    share = {launches[k][0]: round(ms[k] / max(sum(ms), 1e-30), 4) for k in range(len(ms))}
-    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": traffic,
-            "kernel": name, "avg_launch_ms": round(avg_s * 1e3, 4),
-            "flops_per_launch": fl * r, "operator_bytes_per_launch": byts,
-            "launch_time_share": share}
+    out = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+           "frac": round(achieved / peak, 4), "traffic": traffic,
+           "kernel": name, "avg_launch_ms": round(avg_s * 1e3, 4),
+           "flops_per_launch": fl * r, "operator_bytes_per_launch": byts,
+           "launch_time_share": share}
+    if products > 1:
+        out["peak_note"] = f"{PEAK_TFLOPS[base]} TFLOP/s {base.upper()} matrix-core peak / {products:g} products per step"
+    return out
 
 
 def _fingerprint():
@@ -126,47 +146,99 @@ def _timed(fn, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps
 
 
+def exact_rows(S, W, rows, block=8):
+    """(K W)[rows] in FP64 from the library's own kernel sampler (not the oracle)."""
+    import numpy as np
+    W64 = W.cpu().numpy().astype(np.float64)
+    cols = np.arange(S.n)
+    return np.concatenate([S.sample(rows[k:k + block], cols) @ W64 for k in range(0, len(rows), block)])
+
+
 def form_batched(args):
     """48 compressions of uneven N (log-uniform in [8192, 131072]) in one
-    persistent launch per step, r in {32, 64, 128, 256}."""
+    persistent launch per step, r in {32, 64, 128, 256}; every precision form
+    in --precisions uses the same trees and skeletons."""
     import numpy as np
+    import tempfile
     import torch
     import workloads
     import paper_1707_00164_amd as g
     insts = workloads.batched_instances(args.instances)
-    comps, Ws, Us = [], [], []
+    comps, Ws, Us, Ss = [], [], [], []
     t0 = time.perf_counter()
     for w in insts:
         pts = workloads.points(w)
         S = g.KernelSampler(pts, w.kernel, w.h, w.shift)
+        Ss.append(S)
         comps.append(g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol,
                                             kappa=w.kappa, budget=w.budget, seed=w.seed))
         Ws.append(torch.from_numpy(workloads.rhs(w.n, w.r, w.seed).astype(np.float32)).cuda())
         Us.append(torch.empty_like(Ws[-1]))
     t_comp = time.perf_counter() - t0
     log(f"compressed {len(insts)} instances (sum N {sum(w.n for w in insts)}) in {t_comp:.1f} s")
-    for c, W, U in zip(comps, Ws, Us):
-        c.prepare(W.shape[1])
-    g.evaluate_batched(comps, Ws, Us, autotune=True)
-    sec = _timed(lambda: g.evaluate_batched(comps, Ws, Us), args.steps, args.warmup, torch)
-    assert g.batched_status() == 0
-    seq = _timed(lambda: [c.evaluate(W, U) for c, W, U in zip(comps, Ws, Us)], args.steps, args.warmup, torch)
+    check = [0, len(insts) // 2, len(insts) - 1]          # instances whose error is stated
+    rows = {i: workloads.sample_rows(insts[i].n, 32, insts[i].seed) for i in check}
+    exact = {i: exact_rows(Ss[i], Ws[i], rows[i]) for i in check}
     flops = sum(c.stats().flops_per_rhs * W.shape[1] for c, W in zip(comps, Ws))
     dense = sum(2.0 * w.n * w.n * w.r for w in insts)
-    opb = sum(c.stats().operator_bytes for c in comps)
     io = sum(2 * 4 * w.n * w.r for w in insts)
-    t_roof = max(flops / (PEAK_TFLOPS["f32"] * 1e12), (opb + io) / (HBM_GBS * 1e9))
-    out = {"metric": METRIC, "form": "batched", "value": round(dense / sec / 1e9, 2), "unit": "GFLOP/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+    paths = []
+    for c in comps:
+        fd, path = tempfile.mkstemp(suffix=".gofmm")
+        os.close(fd)
+        c.export(path)
+        paths.append(path)
+    results = {}
+    fp32_rows = None
+    for name in args.precisions:
+        if name == "bf16":
+            continue                                      # not an equal-accuracy form
+        prec = {"fp32": g.FP32, "bf16x3": g.BF16X3}[name]
+        cs = comps if name == "fp32" else [g.Compression.load(p, S, storage=prec, near_storage=prec)
+                                           for p, S in zip(paths, Ss)]
+        for c, W in zip(cs, Ws):
+            c.prepare(W.shape[1])
+        g.evaluate_batched(cs, Ws, Us, autotune=True)
+        sec = _timed(lambda: g.evaluate_batched(cs, Ws, Us), args.steps, args.warmup, torch)
+        assert g.batched_status() == 0
+        got = {i: Us[i].cpu().numpy()[rows[i]].astype(np.float64) for i in check}
+        err = max(float(np.linalg.norm(got[i] - exact[i]) / np.linalg.norm(exact[i])) for i in check)
+        if name == "fp32":
+            fp32_rows = got
+        seq = _timed(lambda: [c.evaluate(W, U) for c, W, U in zip(cs, Ws, Us)], args.steps, args.warmup, torch)
+        opb = sum(sum(l[2] for l in c.launches()) for c in cs)   # algorithmic: each block read once
+        base, products = FORM_PEAK["f32" if name == "fp32" else name]
+        peak = PEAK_TFLOPS[base] / products
+        t_roof = max(flops / (peak * 1e12), (opb + io) / (HBM_GBS * 1e9))
+        results[name] = {
+            "value": round(dense / sec / 1e9, 2), "ms_per_step": round(sec * 1e3, 4),
+            "algorithmic_tflops": round(flops / sec / 1e12, 3),
+            "sequential_ms_per_step": round(seq * 1e3, 4), "speedup_vs_sequential": round(seq / sec, 3),
+            "eps2_vs_exact_KW_max_over_checked": err,
+            "eps2_per_checked_instance": {f"{i} (N={insts[i].n}, d={insts[i].dim}, {insts[i].kernel})":
+                                          float(np.linalg.norm(got[i] - exact[i]) / np.linalg.norm(exact[i]))
+                                          for i in check},
+            "rel_diff_vs_fp32_form": (None if name == "fp32" or fp32_rows is None else max(
+                float(np.linalg.norm(got[i] - fp32_rows[i]) / np.linalg.norm(fp32_rows[i])) for i in check)),
+            "roofline": {"bound": "time", "t_roof_ms": round(t_roof * 1e3, 4), "frac": round(t_roof / sec, 4),
+                         "flops": flops, "bytes": opb + io, "peak_tflops": round(peak, 1),
+                         "note": "max(flops / matrix-core peak of the form, operator + W + U bytes / 8 TB/s)"}}
+        log(f"batched {name}: {sec * 1e3:.2f} ms/step ({seq / sec:.2f}x sequential), "
+            f"{flops / sec / 1e12:.1f} TFLOP/s algorithmic, roofline frac {t_roof / sec:.3f}, eps2 {err:.2e}")
+        for c in cs:                                      # host and device copies of this form
+            c.free()
+        torch.cuda.empty_cache()
+    for p in paths:
+        os.unlink(p)
+    first = results[args.precisions[0]] if args.precisions[0] in results else next(iter(results.values()))
+    out = {"metric": METRIC, "form": "batched", "value": first["value"], "unit": "GFLOP/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": first["ms_per_step"],
            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"batched{len(insts)}_loguniform_8192_131072", "instances": len(insts),
                       "sum_n": sum(w.n for w in insts), "r": sorted({w.r for w in insts})},
-           "algorithmic_tflops": round(flops / sec / 1e12, 3),
-           "sequential_ms_per_step": round(seq * 1e3, 4), "speedup_vs_sequential": round(seq / sec, 3),
-           "roofline": {"bound": "time", "t_roof_ms": round(t_roof * 1e3, 4), "frac": round(t_roof / sec, 4),
-                        "flops": flops, "bytes": opb + io,
-                        "note": "max(flops / FP32 matrix-core peak, operator + W + U bytes / 8 TB/s)"},
-           "compress_seconds": round(t_comp, 1)}
+           "results": results, "compress_seconds": round(t_comp, 1)}
+    if "fp32" in results and "bf16x3" in results:
+        out["bf16x3_speedup_vs_fp32"] = round(results["fp32"]["ms_per_step"] / results["bf16x3"]["ms_per_step"], 3)
     print(json.dumps(out), flush=True)
 
 
@@ -204,8 +276,9 @@ def form_large(args):
             c = base if name == "fp32" else g.Compression.load(path, S, storage=sp, near_storage=sn)
             c.prepare(r)
             c.autotune(W, U)
-            sec, prof = time_steps(c, W, U, args.steps, args.warmup, torch, profile=True)
-            rl = roofline(c, prof, r, args.steps, "f32" if name == "fp32" else "bf16")
+            sec, dom, dom_ms, share = time_steps(c, W, U, args.steps, args.warmup, torch)
+            rl = roofline(c, dom, dom_ms, share, r, {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}[name],
+                          near_form={"fp32": "f32", "bf16": "f32", "bf16x3": "bf16x3"}[name])
             res[f"{name}_r{r}"] = {"ms_per_step": round(sec * 1e3, 3),
                                    "value": round(2.0 * w.n * w.n * r / sec / 1e9, 1),
                                    "algorithmic_tflops": round(st.flops_per_rhs * r / sec / 1e12, 2),
@@ -373,9 +446,9 @@ def main():
     if not args.no_autotune:
         comp.autotune(W, U)
     torch.cuda.synchronize()
-    sec, prof = time_steps(comp, W, U, args.steps, args.warmup, torch, profile=True)
+    sec, dom, dom_ms, share = time_steps(comp, W, U, args.steps, args.warmup, torch)
     value = 2.0 * w.n * w.n * w.r / sec / 1e9
-    rl = roofline(comp, prof, w.r, args.steps, "f32")
+    rl = roofline(comp, dom, dom_ms, share, w.r, "f32")
     alg_tflops = st.flops_per_rhs * w.r / sec / 1e12
     log(f"fp32: {sec * 1e3:.3f} ms/step, effective {value:.1f} GFLOP/s, algorithmic "
         f"{alg_tflops:.2f} TFLOP/s; dominant {rl['kernel']} {rl['achieved']} TFLOP/s "
@@ -410,8 +483,8 @@ def main():
         comp3.prepare(w.r)
         if not args.no_autotune:
             comp3.autotune(W, U3)
-        sec3, prof3 = time_steps(comp3, W, U3, args.steps, args.warmup, torch, profile=True)
-        rl3 = roofline(comp3, prof3, w.r, args.steps, "bf16")
+        sec3, dom3, dom3_ms, share3 = time_steps(comp3, W, U3, args.steps, args.warmup, torch)
+        rl3 = roofline(comp3, dom3, dom3_ms, share3, w.r, "bf16x3")
         mixed = {"storage": "bf16x3 (split BF16, 3 BF16 matrix-core products per step)",
                  "value": round(2.0 * w.n * w.n * w.r / sec3 / 1e9, 2), "unit": "GFLOP/s",
                  "ms_per_step": round(sec3 * 1e3, 4), "speedup_vs_fp32": round(sec / sec3, 3),

@@ -203,9 +203,11 @@ int gofmm_launch_info(const gofmm_compression* c, int32_t i, char* name, int32_t
 /*
  * Per-launch timing.  While enabled, every evaluate of c records a HIP event
  * before and after each of its launches on the evaluation stream (no extra
- * synchronization).  gofmm_profile_read waits for the recorded events, writes
- * for each launch i < n the summed milliseconds and the number of recorded
- * launches, and clears the records.
+ * synchronization).  enable: 0 off, 1 every launch, 2 + i launch i only (two
+ * events per evaluate, for timing one launch inside a timed loop).
+ * gofmm_profile_read waits for the recorded events, writes for each launch
+ * i < n the summed milliseconds and the number of recorded launches, and
+ * clears the records.
  */
 int gofmm_profile(gofmm_compression* c, int32_t enable);
 int gofmm_profile_read(gofmm_compression* c, int32_t n, float* total_ms, int32_t* calls);

@@ -240,6 +240,8 @@ extern "C" int gofmm_launch_info(const gofmm_compression* c, int32_t i, char* na
 extern "C" int gofmm_profile(gofmm_compression* c, int32_t enable) {
   return guarded([&] {
     if (!c) fail(GOFMM_EINVAL, "NULL compression");
+    if (enable < 0 || (enable >= 2 && (size_t)(enable - 2) >= c->c.plan.launches.size()))
+      fail(GOFMM_EINVAL, "profile mode out of range");
     device_profile(c->c, enable);
   });
 }
@@ -281,7 +283,7 @@ extern "C" int gofmm_stats(const gofmm_compression* c, gofmm_stats_t* out) {
       out->operator_bytes_phase[p] = x.plan.bytes_phase[p];
     }
     out->operator_bytes = (int64_t)(x.plan.a_f32.size() * 4 + x.plan.a_b16.size() * 2 +
-                                    (x.plan.a_x3hi.size() + x.plan.a_x3lo.size()) * 2);
+                                    x.plan.a_x3.size() * 2);
     out->workspace_rows = x.plan.ws_rows;
   });
 }

@@ -94,6 +94,7 @@ struct DeviceState {
   i64 op_bytes = 0;
   // per-launch timing (HIP events around every launch while enabled)
   bool profiling = false;
+  int prof_only = -1;       // >= 0: record only this launch
   std::vector<hipEvent_t> events;
   size_t ev_used = 0;
   struct Rec { int launch; hipEvent_t a, b; };
@@ -147,11 +148,9 @@ void device_prepare(Compression& c, i64 r_max) {
       const HostPlan& pl = c.plan;
       upload(&d->a_f32, pl.a_f32, d->op_bytes);
       upload(&d->a_b16, pl.a_b16, d->op_bytes);
-      if (!pl.a_x3hi.empty()) {
-        std::vector<uint16_t> both(pl.a_x3hi);
-        both.insert(both.end(), pl.a_x3lo.begin(), pl.a_x3lo.end());
-        d->x3_plane = (i64)pl.a_x3hi.size();
-        upload(&d->a_x3, both, d->op_bytes);
+      if (!pl.a_x3.empty()) {
+        d->x3_plane = pl.x3_plane;
+        upload(&d->a_x3, pl.a_x3, d->op_bytes);
       }
       upload(&d->tasks, pl.tasks, d->op_bytes);
       upload(&d->rows, pl.rows, d->op_bytes);
@@ -302,7 +301,7 @@ static void launch_all(Compression& c, const EvalArgs& e) {
     int grid = 0;
     if (!make_args(c, li, cfg, e, a, grid)) continue;
     KernelFn fn = kernel_for(l, cfg, a.vec != 0);
-    if (d->profiling) {
+    if (d->profiling && (d->prof_only < 0 || d->prof_only == li)) {
       hipEvent_t ev[2];
       for (int q = 0; q < 2; ++q) {
         if (d->ev_used >= d->events.size()) {
@@ -377,9 +376,10 @@ void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
   device_evaluate(c, r, W, ldw, U, ldu, stream);
 }
 
-void device_profile(Compression& c, int on) {
+void device_profile(Compression& c, int mode) {
   if (!c.dev) device_prepare(c, 1);
-  c.dev->profiling = on != 0;
+  c.dev->profiling = mode != 0;
+  c.dev->prof_only = mode >= 2 ? mode - 2 : -1;
 }
 
 // Sum of recorded launch times (ms) and record counts per launch; clears the records.
@@ -399,7 +399,7 @@ void device_profile_read(Compression& c, int n, float* total_ms, int* calls) {
 
 i64 device_footprint(const Compression& c, i64 r_max) {
   const HostPlan& pl = c.plan;
-  i64 b = (i64)(pl.a_f32.size() * 4 + pl.a_b16.size() * 2 + (pl.a_x3hi.size() + pl.a_x3lo.size()) * 2 +
+  i64 b = (i64)(pl.a_f32.size() * 4 + pl.a_b16.size() * 2 + pl.a_x3.size() * 2 +
                 pl.tasks.size() * sizeof(TaskDesc) + pl.rows.size() * 4);
   b += std::max<i64>(1, pl.ws_rows) * ws_cols_for(r_max) * 4;
   // work-item lists: one entry per 32 rows x 32 columns of every task, plus XCD padding

@@ -95,7 +95,8 @@ struct HostPlan {
   std::vector<i32> rows;
   std::vector<float> a_f32;
   std::vector<uint16_t> a_b16;
-  std::vector<uint16_t> a_x3hi, a_x3lo;
+  std::vector<uint16_t> a_x3;        // split BF16: hi plane, then lo plane at x3_plane
+  i64 x3_plane = 0;
   i64 ws_rows = 0;        // 2 * sum of ranks: skeleton weights then potentials
   double flops_phase[4] = {0, 0, 0, 0};     // per right-hand side
   i64 bytes_phase[4] = {0, 0, 0, 0};        // operator bytes read per evaluate

@@ -73,6 +73,27 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
 }
 
 
+// Scheduling groups for one k step: N matrix-core instructions, each followed
+// by at most one LDS read, one LDS write, one global load and VAL vector
+// instructions (groups the step cannot fill stay empty).
+template <int N, int VAL>
+struct Interleave {
+  static __device__ __forceinline__ void run() {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, VAL, 0);
+    Interleave<N - 1, VAL>::run();
+  }
+};
+template <int VAL>
+struct Interleave<0, VAL> {
+  static __device__ __forceinline__ void run() {}
+};
+template <int N, int VAL>
+__device__ __forceinline__ void interleave() { Interleave<N, VAL>::run(); }
+
 // LDS of one block: B only, double-buffered, one k slab per buffer (32 FP32 or
 // 64 BF16 values = 128 bytes per column).  Column c occupies 36 words (the
 // slab and 4 words of padding); its 16-byte chunk q sits at chunk position
@@ -88,6 +109,11 @@ struct Smem {
 };
 
 __device__ __forceinline__ int swz(int c, int q) { return c * 36 + 4 * (q ^ ((c >> 4) & 3)); }
+
+// Sixteen zero bytes in device memory: B elements that read as zero (rows
+// coded ROW_ZERO, columns past r) are loaded from here, so their loads need
+// neither a branch nor a mask.
+static __device__ __attribute__((aligned(16))) float g_zero16[4];
 
 // One BM x BN output tile of task td (rows m0.., columns n0..); accumulate adds
 // the product to the output instead of overwriting it.
@@ -165,11 +191,11 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   };
   const auto Wg = gmem(a.W);
   const auto WSg = gmem(a.WS);
-  // Every load is issued unconditionally and its value is left untouched until
-  // the slab is stored to LDS a slab later, where a bit mask zeroes what must
-  // read as zero (rows coded ROW_ZERO, columns past r): nothing waits for a B
-  // load early and the k loop stays free of branches.
-  unsigned int zmask[BST];                            // bit 4e + q: element (e, q) reads as 0
+  const auto Zg = gmem(static_cast<const float*>(g_zero16));
+  // Every load is issued unconditionally; B elements that read as zero (rows
+  // coded ROW_ZERO, columns past r) come from the zero bytes above.  Nothing
+  // waits for a B load before the slab is stored to LDS a slab later, and the
+  // k loop stays free of branches.
   auto bload = [&]() {
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
@@ -181,53 +207,51 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
         const bool inw = code >= 0;
         const long long idx = inw ? code : -(code + 1);
         const long long ld = inw ? a.ldw : a.ldws;
-        return (inw ? Wg : WSg) + (zr ? 0 : idx * ld);
+        return (inw ? Wg : WSg) + idx * ld;
       };
-      unsigned int zm = 0;
+      // (the row address is made opaque before the select, so the compiler
+      // cannot move its computation into a branch)
       if constexpr (VEC) {                            // rows 16-byte aligned, r % 4 == 0
         const bool zc = col >= a.r;
 #pragma unroll
         for (int e = 0; e < SBR; ++e) {
           bool zr;
-          const auto p = rowp(e, zr);
-          const bool z = zr || zc;
-          rbv[t][e] = *(const __attribute__((address_space(1))) f32x4*)(p + (z ? 0 : col));
-          zm |= z ? 0xfu << (4 * e) : 0u;
+          unsigned long long pa = (unsigned long long)(rowp(e, zr) + col);
+          asm volatile("" : "+v"(pa));
+          const auto q = (zr || zc) ? Zg : (const __attribute__((address_space(1))) float*)pa;
+          rbv[t][e] = *(const __attribute__((address_space(1))) f32x4*)q;
         }
       } else {
 #pragma unroll
         for (int e = 0; e < SBR; ++e) {
           bool zr;
-          const auto p = rowp(e, zr);
+          unsigned long long pa = (unsigned long long)(rowp(e, zr) + col);
+          asm volatile("" : "+v"(pa));
+          const auto p = (const __attribute__((address_space(1))) float*)pa;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const bool z = zr || col + q >= a.r;
-            rbv[t][e][q] = p[z ? 0 : col + q];
-            zm |= z ? 1u << (4 * e + q) : 0u;
-          }
+          for (int q = 0; q < 4; ++q) rbv[t][e][q] = *((zr || col + q >= a.r) ? Zg : p + q);
         }
       }
-      zmask[t] = zm;
     }
   };
-  auto bval = [&](int t, int e, int j) { return (zmask[t] >> (4 * e + j)) & 1u ? 0.f : rbv[t][e][j]; };
-  auto bstore = [&](int buf) {
+  // columns j0 .. j1-1 of each thread's sub-blocks
+  auto bstore = [&](int buf, int j0, int j1) {
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
       const int sub = tid + t * NT;
       if (BSUB % NT == 0 || sub < BSUB) {
         const int cq = sub % (BN / 4), kq = sub / (BN / 4);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = j0; j < j1; ++j) {
           const int w = swz(4 * cq + j, kq);
           if constexpr (F32) {
-            const f32x4 v = {bval(t, 0, j), bval(t, 1, j), bval(t, 2, j), bval(t, 3, j)};
+            const f32x4 v = {rbv[t][0][j], rbv[t][1][j], rbv[t][2][j], rbv[t][3][j]};
             *reinterpret_cast<f32x4*>(&sm.sB[buf][0][w]) = v;
           } else {
             u32x4 hi, lo;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const f32x2 x = {bval(t, 2 * e, j), bval(t, 2 * e + 1, j)};
+              const f32x2 x = {rbv[t][2 * e][j], rbv[t][2 * e + 1][j]};
               const bf16x2 h = __builtin_convertvector(x, bf16x2);
               hi[e] = __builtin_bit_cast(unsigned int, h);
               if constexpr (X3) {
@@ -279,32 +303,33 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
           for (int j = 0; j < TN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][q], bv[j][q], acc[i][j], 0, 0, 0);
     } else {
+      // product-major order: consecutive matrix-core instructions update
+      // different accumulators, so none waits for the previous result (each
+      // element still receives lo*hi, hi*lo, hi*hi in that order)
+      constexpr int NPROD = X3 ? 3 : 1;
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const bf16x8 ah = __builtin_bit_cast(bf16x8, ra[s][0][i]);
+      for (int pr = 0; pr < NPROD; ++pr)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          const bf16x8 bh = __builtin_bit_cast(bf16x8, bfr[bs][0][j]);
-          if constexpr (X3) {
-            const bf16x8 al = __builtin_bit_cast(bf16x8, ra[s][NPL - 1][i]);
-            const bf16x8 bl = __builtin_bit_cast(bf16x8, bfr[bs][NPL - 1][j]);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[i][j], 0, 0, 0);
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            const int pa = (X3 && pr == 0) ? NPL - 1 : 0;    // lo*hi, hi*lo, hi*hi
+            const int pb = (X3 && pr == 1) ? NPL - 1 : 0;
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ra[s][pa][i]),
+                                                                __builtin_bit_cast(bf16x8, bfr[bs][pb][j]),
+                                                                acc[i][j], 0, 0, 0);
           }
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[i][j], 0, 0, 0);
-        }
-      }
     }
   };
 
-  const int ns = td.lda / KSLAB;
+  const int ns = td.lda / KSLAB;                     // k is padded to whole slabs
   if (ns > 0) {
     cload(0);
     bload();
     cload(KSLAB);
 #pragma unroll
     for (int s = 0; s < NS; ++s) aload(s, s);
-    bstore(0);
+    bstore(0, 0, 4);
     bload();
     cload(2 * KSLAB);
   }
@@ -320,11 +345,15 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       // slab kt + 1 into the other buffer (no wave reads it before the
       // barrier below), then the B rows of slab kt + 2 and the codes of
       // slab kt + 3; past the last slab these move data that nobody reads
-      if (s == 0) bstore(buf ^ 1);
+      if (s == 0) bstore(buf ^ 1, 0, 2);
       if (s == 1) {
+        bstore(buf ^ 1, 2, 4);
         bload();
         cload((kt + 3) * KSLAB);
       }
+      // one matrix-core instruction at a time, with the step's LDS traffic,
+      // global loads and vector work placed in its shadow
+      if constexpr (F32) interleave<TM * TN * 4, 12>();
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();

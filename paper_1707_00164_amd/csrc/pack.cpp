@@ -30,8 +30,8 @@ namespace gofmm {
 
 namespace {
 
-// k padding of A blocks (the kernels' k slab: 32 FP32 or 64 BF16 values);
-// rows are padded to 32.
+// k padding of A blocks (one k slab of the kernels: 32 FP32 or 64 BF16
+// values); rows are padded to 32.
 i64 round_up(i64 x, i64 a) { return (x + a - 1) / a * a; }
 i64 kalign(int prec) { return prec == PREC_F32 ? 32 : 64; }
 i64 rows_stored(i64 m) { return round_up(m, 32); }
@@ -253,8 +253,8 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
   }
   pl.a_f32.assign(off[PREC_F32], 0.0f);
   pl.a_b16.assign(off[PREC_BF16], 0);
-  pl.a_x3hi.assign(off[PREC_BF16X3], 0);
-  pl.a_x3lo.assign(off[PREC_BF16X3], 0);
+  pl.x3_plane = off[PREC_BF16X3];
+  pl.a_x3.assign(2 * off[PREC_BF16X3], 0);
 
   // flop and byte accounting per right-hand side (Table 2)
   for (size_t li = 0; li < pl.launches.size(); ++li) {
@@ -315,8 +315,8 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
         for (i64 i = 0; i < m; ++i)
           for (i64 j = 0; j < k; ++j) dst[frag_pos_b16(i, j, lda)] = to_bf16(A[i * k + j]);
       } else {
-        uint16_t* hi = &pl.a_x3hi[td.a_off];
-        uint16_t* lo = &pl.a_x3lo[td.a_off];
+        uint16_t* hi = &pl.a_x3[td.a_off];
+        uint16_t* lo = &pl.a_x3[pl.x3_plane + td.a_off];
         for (i64 i = 0; i < m; ++i)
           for (i64 j = 0; j < k; ++j) {
             const double x = A[i * k + j];

@@ -146,6 +146,19 @@ class KernelSampler:
         self.n = pts.shape[0]
         self.fn = C.cast(lib().gofmm_kernel_sample, SAMPLER)
 
+    def sample(self, I, J) -> np.ndarray:
+        """K(I, J) in FP64 (original indices), from the library's sampler."""
+        I = np.ascontiguousarray(I, dtype=np.int64)
+        J = np.ascontiguousarray(J, dtype=np.int64)
+        out = np.empty((len(I), len(J)), dtype=np.float64)
+        if len(I) and len(J):
+            rc = lib().gofmm_kernel_sample(self.state, len(I), I.ctypes.data_as(C.POINTER(C.c_int64)), len(J),
+                                           J.ctypes.data_as(C.POINTER(C.c_int64)),
+                                           out.ctypes.data_as(C.POINTER(C.c_double)), len(J))
+            if rc != 0:
+                raise GofmmError(rc, "kernel sampler failed")
+        return out
+
     def __del__(self):
         if getattr(self, "state", None) and _lib is not None:
             _lib.gofmm_kernel_free(self.state)
@@ -236,8 +249,10 @@ class Compression:
             out.append((buf.value.decode(), f.value, b.value))
         return out
 
-    def profile(self, enable: bool):
-        _check(lib().gofmm_profile(self.h, 1 if enable else 0))
+    def profile(self, enable: bool, launch: int | None = None):
+        """Per-launch HIP-event timing: off, every launch, or only `launch`."""
+        mode = 0 if not enable else (1 if launch is None else 2 + int(launch))
+        _check(lib().gofmm_profile(self.h, mode))
 
     def profile_read(self):
         """(total ms, record count) per launch since profiling was enabled."""
