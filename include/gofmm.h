@@ -139,9 +139,13 @@ int gofmm_prepare(gofmm_compression* c, int64_t r_max);
  * of n rows in the original order, row-major with leading dimensions ldw,
  * ldu >= r (FP32), and must not overlap.  Every row of U is overwritten.
  * Work is enqueued on `hip_stream` (NULL = default stream) and the call
- * returns without synchronizing.  Concurrent evaluates of one compression
- * must be serialized by the caller (they share its workspace).  r == 0 is a
- * no-op; r > r_max of a previous prepare grows the workspace synchronously.
+ * returns without synchronizing.  Evaluates of one compression must run on
+ * the device in the order they are made (one stream, or streams the caller
+ * orders): they share its workspace, and, when the environment sets
+ * GOFMM_PASSES=1, the counters of its persistent tree passes (the upward and
+ * the downward pass then each run as one launch whose tiles wait for the
+ * tiles they read, through counters that only grow).  r == 0 is a no-op;
+ * r > r_max of a previous prepare grows the workspace synchronously.
  */
 int gofmm_evaluate(gofmm_compression* c, int64_t r,
                    const float* W, int64_t ldw, float* U, int64_t ldu,
@@ -189,6 +193,13 @@ int gofmm_batched_status(int32_t* error);
  * tile is skipped, so a launch always ends.  <= 0 restores the default.
  */
 int gofmm_batched_spin_limit(int64_t polls);
+
+/*
+ * Wait for the device and report the persistent tree passes of c: *error = 1
+ * if a block of one of its passes gave up a dependency wait since the last
+ * call (the same bound as gofmm_batched_spin_limit), else 0.  Clears the flag.
+ */
+int gofmm_evaluate_status(gofmm_compression* c, int32_t* error);
 
 /*
  * Launches of one evaluate, in order.  For launch i: its name (e.g. "n2s_leaf",

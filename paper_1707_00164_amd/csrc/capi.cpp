@@ -21,6 +21,7 @@ void device_profile(Compression& c, int on);
 void device_autotune_batched(int k, Compression* const* c, const i64* r, const float* const* W,
                              const i64* ldw, float* const* U, const i64* ldu, void* stream, int reps);
 int device_batched_status();
+int device_pass_status(Compression& c);
 void device_set_spin_limit(long long v);
 void device_profile_read(Compression& c, int n, float* total_ms, int* calls);
 
@@ -208,6 +209,13 @@ extern "C" int gofmm_batched_status(int32_t* error) {
   return guarded([&] {
     if (!error) fail(GOFMM_EINVAL, "NULL argument");
     *error = device_batched_status();
+  });
+}
+
+extern "C" int gofmm_evaluate_status(gofmm_compression* c, int32_t* error) {
+  return guarded([&] {
+    if (!c || !error) fail(GOFMM_EINVAL, "NULL argument");
+    *error = device_pass_status(c->c);
   });
 }
 

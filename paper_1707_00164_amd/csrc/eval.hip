@@ -58,7 +58,7 @@ static int family_of(const LaunchDesc& l) {
 // 16-byte aligned and r % 4 == 0
 struct Tables {
   KernelFn k[2][3][kNumCfg * kNumFamily];
-  dev::BatchedFn b[2][3][kNumCfg];
+  dev::BatchedFn b[2][3][kNumCfg * 2];   // [cfg * 2]: batched, [cfg * 2 + 1]: tree pass
   Tables() {
     dev::kernels_f32_vec(k[1][PREC_F32], b[1][PREC_F32]);
     dev::kernels_f32_any(k[0][PREC_F32], b[0][PREC_F32]);
@@ -90,7 +90,18 @@ struct DeviceState {
   i64 ws_cols = 0;                  // floats per workspace row allocated
   // work-item lists per (launch, configuration, column tiles)
   std::map<std::tuple<int, int, int>, std::pair<int2*, int>> items;
-  std::map<std::pair<int, i64>, int> tuned;   // (launch, r) -> configuration
+  std::map<std::pair<int, i64>, int> tuned;   // (launch, r) -> configuration; pass segments use -(first + 1)
+  // persistent tree passes: device tables per (first launch, configuration, r)
+  struct Pass {
+    dev::BItem* items = nullptr;
+    int* stage_acc = nullptr;
+    int* ctr_total = nullptr;
+    unsigned long long* ctr = nullptr;    // counters, then the queue head
+    int* error = nullptr;
+    int n_items = 0, n_ctr = 0, grid = 0;
+    unsigned long long epoch = 0, head_base = 0;
+  };
+  std::map<std::tuple<int, int, i64>, Pass> passes;
   i64 op_bytes = 0;
   // per-launch timing (HIP events around every launch while enabled)
   bool profiling = false;
@@ -114,6 +125,13 @@ void device_state_free(DeviceState* d) {
   int cur = -1;
   (void)hipGetDevice(&cur);
   if (d->device >= 0) (void)hipSetDevice(d->device);
+  for (auto& kv : d->passes) {
+    (void)hipFree(kv.second.items);
+    (void)hipFree(kv.second.stage_acc);
+    (void)hipFree(kv.second.ctr_total);
+    (void)hipFree(kv.second.ctr);
+    (void)hipFree(kv.second.error);
+  }
   (void)hipFree(d->a_f32);
   (void)hipFree(d->a_b16);
   (void)hipFree(d->a_x3);
@@ -244,6 +262,151 @@ static int choose_cfg(const Compression& c, int li, i64 r) {
   return bc;
 }
 
+// ------------------------------------------------------------------ persistent tables
+// Node of task t of launch l, and back (the task order of each step is the
+// one pack.cpp builds: leaves left to right, the nodes of a level left to
+// right, every non-root node in heap order for S2S).
+static i64 node_of(const Compression& c, const LaunchDesc& l, i32 t) {
+  const i64 o = t - l.t_begin;
+  switch (l.kind) {
+    case 1: case 6: return ((i64)1 << l.level) - 1 + o;
+    case 2: return 1 + o;
+    default: return c.fl() + o;                   // leaf steps
+  }
+}
+static i32 task_of(const Compression& c, const LaunchDesc& l, i64 node) {
+  switch (l.kind) {
+    case 1: case 6: return l.t_begin + (i32)(node - (((i64)1 << l.level) - 1));
+    case 2: return l.t_begin + (i32)(node - 1);
+    default: return l.t_begin + (i32)(node - c.fl());
+  }
+}
+static int find_launch(const HostPlan& pl, int kind, int level) {
+  for (int j = 0; j < (int)pl.launches.size(); ++j)
+    if (pl.launches[j].kind == kind && (level < 0 || pl.launches[j].level == level)) return j;
+  return -1;
+}
+
+// Work items of the launches [j0[i], j1[i]) of every instance i, in stage
+// order (launch j of every instance before launch j + 1 of any; longest k
+// first within that), with their dependencies:
+//   N2S of a node     waits for the N2S tasks of its two children;
+//   S2S               waits for the whole upward pass (its last stage: every
+//                     task of a stage waited for its children, and every task
+//                     has at least one tile since ranks are >= 1);
+//   S2N of a node     waits for its own S2S task and for the task that
+//                     finished its parent's potential (S2N, or S2S at level 1);
+//   leaf output       waits for the task that finished the leaf's potential;
+//   L2L (split leaf)  waits for the leaf's S2N-leaf task.
+// Dependencies on launches outside the ranges are met by stream order.
+// Counters: one per stage, then one per task.
+static void build_pass_tables(int k, Compression* const* c, const i64* r, const int* j0, const int* j1, int cfg,
+                              std::vector<dev::BItem>& items, std::vector<int>& stage_acc,
+                              std::vector<int>& ctr_total) {
+  const Cfg& g = kCfgs[cfg];
+  items.clear();
+  stage_acc.clear();
+  ctr_total.clear();
+  int max_l = 0;
+  for (int i = 0; i < k; ++i) max_l = std::max(max_l, j1[i]);
+  std::vector<std::vector<int>> sid(k);             // stage of launch j of instance i, or -1
+  std::vector<int> tbase;                           // first task counter (relative) per stage
+  std::vector<int> stage_tiles;
+  int S = 0, T = 0;
+  for (int j = 0; j < max_l; ++j)
+    for (int i = 0; i < k; ++i) {
+      if ((int)sid[i].size() < max_l) sid[i].assign(max_l, -1);
+      if (j < j0[i] || j >= j1[i]) continue;
+      const LaunchDesc& l = c[i]->plan.launches[j];
+      sid[i][j] = S++;
+      tbase.push_back(T);
+      T += l.t_end - l.t_begin;
+      stage_acc.push_back(l.accumulate);
+    }
+  ctr_total.assign(S + T, 0);
+  auto tiles_of = [&](int i, i32 t) {
+    const int ntn = (int)((r[i] + g.bn - 1) / g.bn);
+    return (int)((c[i]->plan.tasks[t].m + g.bm - 1) / g.bm) * ntn;
+  };
+  // tile counts per stage and per task
+  for (int i = 0; i < k; ++i)
+    for (int j = j0[i]; j < j1[i]; ++j) {
+      const LaunchDesc& l = c[i]->plan.launches[j];
+      for (i32 t = l.t_begin; t < l.t_end; ++t) {
+        const int n = tiles_of(i, t);
+        ctr_total[sid[i][j]] += n;
+        ctr_total[S + tbase[sid[i][j]] + (t - l.t_begin)] += n;
+      }
+    }
+  auto task_ctr = [&](int i, int j, i32 t) {
+    const LaunchDesc& l = c[i]->plan.launches[j];
+    return S + tbase[sid[i][j]] + (t - l.t_begin);
+  };
+  auto in_range = [&](int i, int j) { return j >= 0 && j >= j0[i] && j < j1[i]; };
+  struct T2 { dev::BItem it; i64 cost; };
+  std::vector<T2> pos;
+  for (int j = 0; j < max_l; ++j) {
+    pos.clear();
+    for (int i = 0; i < k; ++i) {
+      if (j < j0[i] || j >= j1[i]) continue;
+      const Compression& cc = *c[i];
+      const HostPlan& pl = cc.plan;
+      const LaunchDesc& l = pl.launches[j];
+      const int D = cc.depth;
+      const int ntn = (int)((r[i] + g.bn - 1) / g.bn);
+      const int j_s2s = find_launch(pl, 2, -1);
+      for (i32 t = l.t_begin; t < l.t_end; ++t) {
+        int dep[2] = {-1, -1}, need[2] = {0, 0}, nd = 0;
+        auto add_task = [&](int jj, i64 node) {
+          if (!in_range(i, jj)) return;
+          const i32 tt = task_of(cc, pl.launches[jj], node);
+          dep[nd] = task_ctr(i, jj, tt);
+          need[nd] = tiles_of(i, tt);
+          ++nd;
+        };
+        const i64 h = node_of(cc, l, t);
+        if (l.kind == 1) {                          // N2S of a node: its children
+          for (i64 ch : {2 * h + 1, 2 * h + 2})
+            add_task(l.level + 1 == D ? find_launch(pl, 0, -1) : find_launch(pl, 1, l.level + 1), ch);
+        } else if (l.kind == 2) {                   // S2S: the whole upward pass
+          const int ju = D >= 2 ? find_launch(pl, 1, 1) : find_launch(pl, 0, -1);
+          if (in_range(i, ju)) {
+            dep[0] = sid[i][ju];
+            need[0] = ctr_total[sid[i][ju]];
+            nd = 1;
+          }
+        } else if (l.kind == 6) {                   // S2N of node h at level >= 2
+          add_task(j_s2s, h);
+          const i64 p = (h - 1) / 2;
+          add_task(l.level >= 3 ? find_launch(pl, 6, l.level - 1) : j_s2s, p);
+        } else if (l.kind == 3 || l.kind == 4) {    // leaf output / S2N at the leaf
+          if (D >= 2) add_task(find_launch(pl, 6, D), h);
+          else if (D == 1) add_task(j_s2s, h);
+        } else if (l.kind == 5) {                   // L2L after the leaf's S2N
+          add_task(find_launch(pl, 4, -1), h);
+        }
+        const int tc = task_ctr(i, j, t);
+        for (int mt = 0; mt * g.bm < pl.tasks[t].m; ++mt)
+          for (int nt = 0; nt < ntn; ++nt) {
+            dev::BItem it;
+            it.inst = i;
+            it.stage = sid[i][j];
+            it.task = t;
+            it.tile = (mt << 16) | nt;
+            it.tctr = tc;
+            it.dep[0] = dep[0];
+            it.dep[1] = dep[1];
+            it.need[0] = need[0];
+            it.need[1] = need[1];
+            pos.push_back({it, (i64)std::max(pl.tasks[t].lda, 32)});
+          }
+      }
+    }
+    std::stable_sort(pos.begin(), pos.end(), [](const T2& x, const T2& y) { return x.cost > y.cost; });
+    for (auto& t2 : pos) items.push_back(t2.it);
+  }
+}
+
 struct EvalArgs {
   i64 r;
   const float* W;
@@ -292,34 +455,194 @@ static int cfg_for(Compression& c, int li, i64 r) {
   return it != c.dev->tuned.end() ? it->second : choose_cfg(c, li, r);
 }
 
+static bool rows_vec(const float* W, i64 ldw, const float* U, i64 ldu, i64 r) {
+  return ((uintptr_t)W % 16 == 0) && ((uintptr_t)U % 16 == 0) && ldw % 4 == 0 && ldu % 4 == 0 && r % 4 == 0;
+}
+
+static dev::BInst make_inst(Compression& c, int prec, i64 r, const float* W, i64 ldw, float* U, i64 ldu) {
+  DeviceState* d = c.dev;
+  dev::BInst in;
+  in.tasks = d->tasks;
+  in.rows = d->rows;
+  in.A = prec == PREC_F32 ? (const void*)d->a_f32 : prec == PREC_BF16 ? (const void*)d->a_b16 : (const void*)d->a_x3;
+  in.plane = d->x3_plane;
+  in.W = W;
+  in.ldw = ldw;
+  in.U = U;
+  in.ldu = ldu;
+  in.WS = d->ws;
+  in.ldws = ws_cols_for(r);
+  in.r = (int)r;
+  in.vec = rows_vec(W, ldw, U, ldu, r);
+  return in;
+}
+
+static long long& spin_limit_ref() {
+  static long long lim = 1ll << 21;
+  return lim;
+}
+
+static int persistent_cap(int prec, int cfg, int which) {
+  static std::map<std::tuple<int, int, int>, int> cache;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find({prec, cfg, which});
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0, devid = 0;
+  HIP_OK(hipGetDevice(&devid));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tables().b[1][prec][cfg * 2 + which], dev::NT, 0));
+  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
+  const int cap = std::max(1, per_cu) * std::max(1, cus);
+  cache[{prec, cfg, which}] = cap;
+  return cap;
+}
+
+// Segments of one evaluate.  By default every launch runs on its own.  With
+// GOFMM_PASSES=1 the N2S launches (upward pass) and the S2N level launches
+// (downward pass) each run as one persistent launch with per-task
+// dependencies (when they hold two or more launches).  Measured on MI355X the
+// separate launches are faster: the persistent passes pay device-coherent
+// (L2-bypassing) accesses for every row they hand between tiles, while kernel
+// boundaries pay one cache write-back per launch.
+struct Seg { int j0, j1; bool pass; };
+static std::vector<Seg> segments(const HostPlan& pl) {
+  const char* ev = std::getenv("GOFMM_PASSES");
+  const bool off = !(ev && ev[0] == '1');
+  std::vector<Seg> out;
+  const int n = (int)pl.launches.size();
+  for (int j = 0; j < n;) {
+    const int kind = pl.launches[j].kind;
+    const int grp = (kind == 0 || kind == 1) ? 1 : kind == 6 ? 2 : 0;
+    int e = j + 1;
+    if (grp) {
+      while (e < n) {
+        const int k2 = pl.launches[e].kind;
+        if (((k2 == 0 || k2 == 1) ? 1 : k2 == 6 ? 2 : 0) != grp) break;
+        ++e;
+      }
+    }
+    if (!off && grp && e - j >= 2) {
+      out.push_back({j, e, true});
+    } else {
+      for (int q = j; q < e; ++q) out.push_back({q, q + 1, false});
+    }
+    j = e;
+  }
+  return out;
+}
+
+static DeviceState::Pass& pass_for(Compression& c, const Seg& sg, int cfg, i64 r) {
+  DeviceState* d = c.dev;
+  const auto key = std::make_tuple(sg.j0, cfg, r);
+  auto it = d->passes.find(key);
+  if (it != d->passes.end()) return it->second;
+  Compression* cp = &c;
+  std::vector<dev::BItem> items;
+  std::vector<int> acc, tot;
+  build_pass_tables(1, &cp, &r, &sg.j0, &sg.j1, cfg, items, acc, tot);
+  DeviceState::Pass P;
+  P.n_items = (int)items.size();
+  P.n_ctr = (int)tot.size();
+  P.grid = std::max(1, std::min(P.n_items, persistent_cap(c.plan.launches[sg.j0].prec, cfg, 1)));
+  try {
+    if (!items.empty()) {
+      HIP_OK(hipMalloc((void**)&P.items, items.size() * sizeof(dev::BItem)));
+      HIP_OK(hipMemcpy(P.items, items.data(), items.size() * sizeof(dev::BItem), hipMemcpyHostToDevice));
+    }
+    HIP_OK(hipMalloc((void**)&P.stage_acc, std::max<size_t>(1, acc.size()) * sizeof(int)));
+    if (!acc.empty()) HIP_OK(hipMemcpy(P.stage_acc, acc.data(), acc.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_OK(hipMalloc((void**)&P.ctr_total, std::max<size_t>(1, tot.size()) * sizeof(int)));
+    if (!tot.empty()) HIP_OK(hipMemcpy(P.ctr_total, tot.data(), tot.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_OK(hipMalloc((void**)&P.ctr, (tot.size() + 1) * sizeof(unsigned long long)));
+    HIP_OK(hipMemset(P.ctr, 0, (tot.size() + 1) * sizeof(unsigned long long)));
+    HIP_OK(hipMalloc((void**)&P.error, sizeof(int)));
+    HIP_OK(hipMemset(P.error, 0, sizeof(int)));
+    HIP_OK(hipDeviceSynchronize());
+  } catch (...) {
+    (void)hipFree(P.items);
+    (void)hipFree(P.stage_acc);
+    (void)hipFree(P.ctr_total);
+    (void)hipFree(P.ctr);
+    (void)hipFree(P.error);
+    throw;
+  }
+  return d->passes[key] = P;
+}
+
+// One persistent launch of a pass segment.  Its counters only grow, so the
+// launch waits for epoch * (tiles per launch) + need and nothing is cleared;
+// launches of one compression must therefore run in the order they are made.
+static void launch_pass(Compression& c, const Seg& sg, int cfg, const EvalArgs& e) {
+  DeviceState::Pass& P = pass_for(c, sg, cfg, e.r);
+  if (P.n_items == 0) return;
+  const int prec = c.plan.launches[sg.j0].prec;
+  dev::BArgs a;
+  a.inst = nullptr;
+  a.one = make_inst(c, prec, e.r, e.W, e.ldw, e.U, e.ldu);
+  a.items = P.items;
+  a.n_items = P.n_items;
+  a.stage_acc = P.stage_acc;
+  a.ctr_total = P.ctr_total;
+  a.ctr = P.ctr;
+  a.head = P.ctr + P.n_ctr;
+  a.head_base = P.head_base;
+  a.epoch = P.epoch;
+  a.error = P.error;
+  a.spin_limit = spin_limit_ref();
+  hipLaunchKernelGGL(tables().b[a.one.vec ? 1 : 0][prec][cfg * 2 + 1], dim3(P.grid), dim3(dev::NT), 0, e.stream, a);
+  HIP_OK(hipGetLastError());
+  P.epoch += 1;
+  P.head_base += (unsigned long long)P.n_items + (unsigned long long)P.grid;
+}
+
+static int cfg_for_seg(Compression& c, const Seg& sg, i64 r) {
+  if (!sg.pass) return cfg_for(c, sg.j0, r);
+  const int f = forced_tile();
+  if (f >= 0) return f;
+  auto it = c.dev->tuned.find({-(sg.j0 + 1), r});
+  return it != c.dev->tuned.end() ? it->second : choose_cfg(c, sg.j0, r);
+}
+
+static void launch_seg(Compression& c, const Seg& sg, int cfg, const EvalArgs& e, bool overwrite_only = false) {
+  if (sg.pass) {
+    launch_pass(c, sg, cfg, e);
+    return;
+  }
+  dev::KArgs a;
+  int grid = 0;
+  if (!make_args(c, sg.j0, cfg, e, a, grid)) return;
+  LaunchDesc lo = c.plan.launches[sg.j0];
+  if (overwrite_only) {              // timing runs: accumulating launches would change their output
+    if (lo.kind == 6) lo.kind = 1;
+    lo.accumulate = 0;
+  }
+  hipLaunchKernelGGL(kernel_for(lo, cfg, a.vec != 0), dim3(grid), dim3(dev::NT), 0, e.stream, a);
+  HIP_OK(hipGetLastError());
+}
+
 static void launch_all(Compression& c, const EvalArgs& e) {
   DeviceState* d = c.dev;
-  for (int li = 0; li < (int)c.plan.launches.size(); ++li) {
-    const LaunchDesc& l = c.plan.launches[li];
-    const int cfg = cfg_for(c, li, e.r);
-    dev::KArgs a;
-    int grid = 0;
-    if (!make_args(c, li, cfg, e, a, grid)) continue;
-    KernelFn fn = kernel_for(l, cfg, a.vec != 0);
-    if (d->profiling && (d->prof_only < 0 || d->prof_only == li)) {
-      hipEvent_t ev[2];
-      for (int q = 0; q < 2; ++q) {
-        if (d->ev_used >= d->events.size()) {
-          hipEvent_t x;
-          HIP_OK(hipEventCreate(&x));
-          d->events.push_back(x);
-        }
-        ev[q] = d->events[d->ev_used++];
-      }
-      HIP_OK(hipEventRecord(ev[0], e.stream));
-      hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::NT), 0, e.stream, a);
-      HIP_OK(hipGetLastError());
-      HIP_OK(hipEventRecord(ev[1], e.stream));
-      d->pending.push_back({li, ev[0], ev[1]});
-    } else {
-      hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::NT), 0, e.stream, a);
-      HIP_OK(hipGetLastError());
+  for (const Seg& sg : segments(c.plan)) {
+    const int cfg = cfg_for_seg(c, sg, e.r);
+    const bool rec = d->profiling && (d->prof_only < 0 || (d->prof_only >= sg.j0 && d->prof_only < sg.j1));
+    if (!rec) {
+      launch_seg(c, sg, cfg, e);
+      continue;
     }
+    // a pass segment is recorded under its first launch
+    hipEvent_t ev[2];
+    for (int q = 0; q < 2; ++q) {
+      if (d->ev_used >= d->events.size()) {
+        hipEvent_t x;
+        HIP_OK(hipEventCreate(&x));
+        d->events.push_back(x);
+      }
+      ev[q] = d->events[d->ev_used++];
+    }
+    HIP_OK(hipEventRecord(ev[0], e.stream));
+    launch_seg(c, sg, cfg, e);
+    HIP_OK(hipEventRecord(ev[1], e.stream));
+    d->pending.push_back({sg.j0, ev[0], ev[1]});
   }
 }
 
@@ -332,7 +655,7 @@ void device_evaluate(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
   launch_all(c, EvalArgs{r, W, ldw, U, ldu, (hipStream_t)stream});
 }
 
-// Time every configuration of every launch for this r and keep the fastest.
+// Time every configuration of every segment for this r and keep the fastest.
 void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i64 ldu, void* stream,
                      int reps) {
   device_evaluate(c, r, W, ldw, U, ldu, stream);          // prepares and warms up
@@ -343,37 +666,46 @@ void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
   const EvalArgs e{r, W, ldw, U, ldu, st};
   const bool prof = c.dev->profiling;
   c.dev->profiling = false;
-  for (int li = 0; li < (int)c.plan.launches.size(); ++li) {
+  for (const Seg& sg : segments(c.plan)) {
     float best = 1e30f;
-    int bc = choose_cfg(c, li, r);
+    int bc = choose_cfg(c, sg.j0, r);
     for (int q = 0; q < kNumCfg; ++q) {
-      dev::KArgs a;
-      int grid = 0;
-      if (!make_args(c, li, q, e, a, grid)) continue;
-      // accumulating launches would change their output; time them overwriting
-      LaunchDesc lo = c.plan.launches[li];
-      if (lo.kind == 6) lo.kind = 1;
-      lo.accumulate = 0;
-      KernelFn fn = kernel_for(lo, q, a.vec != 0);
-      hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::NT), 0, st, a);
+      launch_seg(c, sg, q, e, true);
       HIP_OK(hipEventRecord(e0, st));
-      for (int t = 0; t < reps; ++t) hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::NT), 0, st, a);
+      for (int t = 0; t < reps; ++t) launch_seg(c, sg, q, e, true);
       HIP_OK(hipEventRecord(e1, st));
       HIP_OK(hipEventSynchronize(e1));
       float ms = 0.f;
       HIP_OK(hipEventElapsedTime(&ms, e0, e1));
       if (ms < best) { best = ms; bc = q; }
       if (std::getenv("GOFMM_TUNE_LOG"))
-        std::fprintf(stderr, "tune %s r=%lld cfg %dx%d: %.4f ms\n", c.plan.launches[li].name.c_str(),
-                     (long long)r, kCfgs[q].bm, kCfgs[q].bn, ms / reps);
+        std::fprintf(stderr, "tune %s%s r=%lld cfg %dx%d: %.4f ms\n", c.plan.launches[sg.j0].name.c_str(),
+                     sg.pass ? " (pass)" : "", (long long)r, kCfgs[q].bm, kCfgs[q].bn, ms / reps);
     }
-    c.dev->tuned[{li, r}] = bc;
+    c.dev->tuned[{sg.pass ? -(sg.j0 + 1) : sg.j0, r}] = bc;
   }
   c.dev->profiling = prof;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   // the timing runs overwrote intermediate rows: recompute a clean result
   device_evaluate(c, r, W, ldw, U, ldu, stream);
+}
+
+// Error flags of the compression's persistent passes (1 if a dependency wait
+// hit its poll bound since the last call); waits for the device.
+int device_pass_status(Compression& c) {
+  if (!c.dev) return 0;
+  HIP_OK(hipDeviceSynchronize());
+  int any = 0;
+  for (auto& kv : c.dev->passes) {
+    int f = 0;
+    HIP_OK(hipMemcpy(&f, kv.second.error, sizeof(int), hipMemcpyDeviceToHost));
+    if (f) {
+      any = 1;
+      HIP_OK(hipMemset(kv.second.error, 0, sizeof(int)));
+    }
+  }
+  return any;
 }
 
 void device_profile(Compression& c, int mode) {
@@ -410,10 +742,6 @@ i64 device_footprint(const Compression& c, i64 r_max) {
 }
 
 // ------------------------------------------------------------------ batched launch
-static long long& spin_limit_ref() {
-  static long long v = 1ll << 21;
-  return v;
-}
 void device_set_spin_limit(long long v) { spin_limit_ref() = v > 0 ? v : (1ll << 21); }
 
 static int batch_prec(int k, Compression* const* c) {
@@ -432,49 +760,6 @@ int device_batch_precision(Compression& c) {
   return batch_prec(1, &p);
 }
 
-// Stage-major queue: stage j of every instance precedes stage j + 1 of any;
-// within a stage position, tiles are ordered longest-k first.  need[s] is the
-// tile count of stage s's predecessor.
-static void build_batch_tables(int k, Compression* const* c, const i64* r, int cfg, std::vector<dev::BItem>& items,
-                               std::vector<int>& prev, std::vector<int>& need, std::vector<int>& acc) {
-  const Cfg& g = kCfgs[cfg];
-  items.clear();
-  prev.clear();
-  need.clear();
-  acc.clear();
-  std::vector<int> own;
-  std::vector<int> last(k, -1);
-  size_t max_l = 0;
-  for (int i = 0; i < k; ++i) max_l = std::max(max_l, c[i]->plan.launches.size());
-  struct T { dev::BItem it; i64 cost; };
-  std::vector<T> pos;
-  for (size_t j = 0; j < max_l; ++j) {
-    pos.clear();
-    for (int i = 0; i < k; ++i) {
-      const HostPlan& pl = c[i]->plan;
-      if (j >= pl.launches.size()) continue;
-      const LaunchDesc& l = pl.launches[j];
-      const int sid = (int)prev.size();
-      const int ntn = (int)((r[i] + g.bn - 1) / g.bn);
-      int count = 0;
-      for (i32 t = l.t_begin; t < l.t_end; ++t)
-        for (int mt = 0; mt * g.bm < pl.tasks[t].m; ++mt)
-          for (int nt = 0; nt < ntn; ++nt) {
-            pos.push_back({{i, sid, t, (mt << 16) | nt}, (i64)std::max(pl.tasks[t].lda, 32)});
-            ++count;
-          }
-      prev.push_back(last[i]);
-      own.push_back(count);
-      acc.push_back(l.accumulate);
-      last[i] = sid;
-    }
-    std::stable_sort(pos.begin(), pos.end(), [](const T& x, const T& y) { return x.cost > y.cost; });
-    for (auto& t : pos) items.push_back(t.it);
-  }
-  need.resize(prev.size());
-  for (size_t s2 = 0; s2 < prev.size(); ++s2) need[s2] = prev[s2] < 0 ? 0 : own[prev[s2]];
-}
-
 static int batch_cfg_model(int k, Compression* const* c, const i64* r) {
   double best = 1e300;
   int bc = 0;
@@ -491,21 +776,6 @@ static int batch_cfg_model(int k, Compression* const* c, const i64* r) {
   return bc;
 }
 
-static int batch_grid_cap(int prec, int cfg) {
-  static std::map<std::pair<int, int>, int> cache;
-  static std::mutex mu;
-  std::lock_guard<std::mutex> g(mu);
-  auto it = cache.find({prec, cfg});
-  if (it != cache.end()) return it->second;
-  int per_cu = 0, cus = 0, devid = 0;
-  HIP_OK(hipGetDevice(&devid));
-  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tables().b[1][prec][cfg], dev::NT, 0));
-  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
-  const int cap = std::max(1, per_cu) * std::max(1, cus);
-  cache[{prec, cfg}] = cap;
-  return cap;
-}
-
 BatchRing::~BatchRing() {
   for (auto& s : slot) {
     if (s.ev) (void)hipEventSynchronize((hipEvent_t)s.ev);
@@ -518,17 +788,19 @@ BatchRing::~BatchRing() {
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // One batched launch through a staging slot: the host tables go to pinned
-// memory, one async copy moves them (with the zeroed counters) to the device,
-// the kernel runs, and the error flag is copied back to pinned memory.
+// memory, one async copy moves them (with zeroed counters) to the device, the
+// kernel runs, and the error flag is copied back to pinned memory.
 void ring_launch(BatchRing& ring, int k, Compression* const* c, const i64* r, const float* const* W,
                  const i64* ldw, float* const* U, const i64* ldu, hipStream_t st, int cfg) {
   const int prec = batch_prec(k, c);
   std::vector<dev::BItem> items;
-  std::vector<int> prev, need, acc;
-  build_batch_tables(k, c, r, cfg, items, prev, need, acc);
-  const int ns = (int)prev.size();
-  const size_t o_cnt = 0, n_cnt = (size_t)(ns + 2) * sizeof(int);
-  const size_t o_tab = align256(o_cnt + n_cnt), n_tab = (size_t)3 * ns * sizeof(int);
+  std::vector<int> acc, tot;
+  std::vector<int> j0(k, 0), j1(k);
+  for (int i = 0; i < k; ++i) j1[i] = (int)c[i]->plan.launches.size();
+  build_pass_tables(k, c, r, j0.data(), j1.data(), cfg, items, acc, tot);
+  const int ns = (int)acc.size(), nc = (int)tot.size();
+  const size_t o_cnt = 0, n_cnt = (size_t)(nc + 1) * sizeof(unsigned long long);
+  const size_t o_tab = align256(o_cnt + n_cnt), n_tab = (size_t)(ns + nc) * sizeof(int);
   const size_t o_inst = align256(o_tab + n_tab), n_inst = (size_t)k * sizeof(dev::BInst);
   const size_t o_item = align256(o_inst + n_inst), n_item = items.size() * sizeof(dev::BItem);
   const size_t o_err = align256(o_item + n_item);
@@ -557,49 +829,36 @@ void ring_launch(BatchRing& ring, int k, Compression* const* c, const i64* r, co
   char* h = s.host;
   std::memset(h + o_cnt, 0, n_cnt);
   int* tab = reinterpret_cast<int*>(h + o_tab);
-  for (int q = 0; q < ns; ++q) {
-    tab[q] = prev[q];
-    tab[ns + q] = need[q];
-    tab[2 * ns + q] = acc[q];
-  }
+  for (int q = 0; q < ns; ++q) tab[q] = acc[q];
+  for (int q = 0; q < nc; ++q) tab[ns + q] = tot[q];
   dev::BInst* in = reinterpret_cast<dev::BInst*>(h + o_inst);
   bool all_vec = true;
   for (int i = 0; i < k; ++i) {
-    DeviceState* d = c[i]->dev;
-    in[i].tasks = d->tasks;
-    in[i].rows = d->rows;
-    in[i].A = prec == PREC_F32 ? (const void*)d->a_f32 : prec == PREC_BF16 ? (const void*)d->a_b16 : (const void*)d->a_x3;
-    in[i].plane = d->x3_plane;
-    in[i].W = W[i];
-    in[i].ldw = ldw[i];
-    in[i].U = U[i];
-    in[i].ldu = ldu[i];
-    in[i].WS = d->ws;
-    in[i].ldws = ws_cols_for(r[i]);
-    in[i].r = (int)r[i];
-    in[i].vec = ((uintptr_t)W[i] % 16 == 0) && ((uintptr_t)U[i] % 16 == 0) && ldw[i] % 4 == 0 && ldu[i] % 4 == 0 && r[i] % 4 == 0;
+    in[i] = make_inst(*c[i], prec, r[i], W[i], ldw[i], U[i], ldu[i]);
     all_vec = all_vec && in[i].vec;
   }
   if (n_item) std::memcpy(h + o_item, items.data(), n_item);
   *reinterpret_cast<int*>(h + o_err) = 0;
-  HIP_OK(hipMemcpyAsync(s.dev, h, o_err, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(s.dev, h, o_err + sizeof(int), hipMemcpyHostToDevice, st));
   if (!items.empty()) {
     dev::BArgs a;
     char* dv = s.dev;
     a.inst = reinterpret_cast<const dev::BInst*>(dv + o_inst);
+    a.one = in[0];
     a.items = reinterpret_cast<const dev::BItem*>(dv + o_item);
     a.n_items = (int)items.size();
-    a.stage_prev = reinterpret_cast<const int*>(dv + o_tab);
-    a.stage_need = a.stage_prev + ns;
-    a.stage_acc = a.stage_prev + 2 * ns;
-    a.done = reinterpret_cast<int*>(dv + o_cnt);
-    a.head = a.done + ns;
-    a.error = a.done + ns + 1;
+    a.stage_acc = reinterpret_cast<const int*>(dv + o_tab);
+    a.ctr_total = a.stage_acc + ns;
+    a.ctr = reinterpret_cast<unsigned long long*>(dv + o_cnt);
+    a.head = a.ctr + nc;
+    a.head_base = 0;
+    a.epoch = 0;
+    a.error = reinterpret_cast<int*>(dv + o_err);
     a.spin_limit = spin_limit_ref();
-    const int grid = std::max(1, std::min(a.n_items, batch_grid_cap(prec, cfg)));
-    hipLaunchKernelGGL(tables().b[all_vec ? 1 : 0][prec][cfg], dim3(grid), dim3(dev::NT), 0, st, a);
+    const int grid = std::max(1, std::min(a.n_items, persistent_cap(prec, cfg, 0)));
+    hipLaunchKernelGGL(tables().b[all_vec ? 1 : 0][prec][cfg * 2], dim3(grid), dim3(dev::NT), 0, st, a);
     HIP_OK(hipGetLastError());
-    HIP_OK(hipMemcpyAsync(h + o_err, dv + o_cnt + (size_t)(ns + 1) * sizeof(int), sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(h + o_err, dv + o_err, sizeof(int), hipMemcpyDeviceToHost, st));
   }
   HIP_OK(hipEventRecord((hipEvent_t)s.ev, st));
   s.err_off = o_err;

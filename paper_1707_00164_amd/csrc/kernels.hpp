@@ -136,7 +136,12 @@ static __device__ __attribute__((aligned(16))) float g_zero16[4];
 // v_mfma_f32_32x32x16_bf16; split BF16 three (lo*hi, hi*lo, hi*hi).  The k
 // order of the products is the same for every tile shape, so every shape
 // gives the same bits.
-template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
+// COH (persistent launches): the tile's B rows, its output rows and the rows
+// it accumulates into are read and written with device-coherent accesses
+// (they bypass the per-XCD L2 caches, which the XCDs do not keep coherent
+// with each other), so a tile can consume rows that a tile on another XCD
+// produced in the same launch without cache write-backs or invalidations.
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC, bool COH = false>
 __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, int m0, int n0, bool accumulate,
                                           Smem<PREC, BM, BN>& sm) {
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 32, TN = WTN / 32;
@@ -219,7 +224,15 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
           unsigned long long pa = (unsigned long long)(rowp(e, zr) + col);
           asm volatile("" : "+v"(pa));
           const auto q = (zr || zc) ? Zg : (const __attribute__((address_space(1))) float*)pa;
-          rbv[t][e] = *(const __attribute__((address_space(1))) f32x4*)q;
+          if constexpr (COH) {
+            typedef unsigned long long u64 __attribute__((address_space(1)));
+            const unsigned long long lo = __hip_atomic_load((u64*)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long hi = __hip_atomic_load((u64*)q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            rbv[t][e] = f32x4{__builtin_bit_cast(float, (unsigned int)lo), __builtin_bit_cast(float, (unsigned int)(lo >> 32)),
+                              __builtin_bit_cast(float, (unsigned int)hi), __builtin_bit_cast(float, (unsigned int)(hi >> 32))};
+          } else {
+            rbv[t][e] = *(const __attribute__((address_space(1))) f32x4*)q;
+          }
         }
       } else {
 #pragma unroll
@@ -229,7 +242,14 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
           asm volatile("" : "+v"(pa));
           const auto p = (const __attribute__((address_space(1))) float*)pa;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) rbv[t][e][q] = *((zr || col + q >= a.r) ? Zg : p + q);
+          for (int q = 0; q < 4; ++q) {
+            const auto x = (zr || col + q >= a.r) ? Zg : p + q;
+            if constexpr (COH)
+              rbv[t][e][q] = __hip_atomic_load((__attribute__((address_space(1))) float*)x, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+            else
+              rbv[t][e][q] = *x;
+          }
         }
       }
     }
@@ -373,8 +393,15 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       for (int j = 0; j < TN; ++j) {
         const int col = n0 + wc * WTN + j * 32 + li;
         if (col < a.r) {
-          if (accumulate) p[col] += acc[i][j][v];
-          else p[col] = acc[i][j][v];
+          if constexpr (COH) {
+            auto q = (__attribute__((address_space(1))) float*)(p + col);
+            const float base = accumulate ? __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.f;
+            __hip_atomic_store(q, accumulate ? base + acc[i][j][v] : acc[i][j][v], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            if (accumulate) p[col] += acc[i][j][v];
+            else p[col] = acc[i][j][v];
+          }
         }
       }
     }
@@ -405,15 +432,21 @@ __global__ __launch_bounds__(NT) void leaf_tiles(KArgs a) { gemm_tiles<PREC, BM,
 
 typedef void (*KernelFn)(KArgs);
 
-// ------------------------------------------------------------ batched launch
-// Many compressions in one persistent launch.  Every (instance, step) pair is
-// a stage; stages of one instance run in their evaluation order and stages of
-// different instances are independent.  Work items (tiles) sit in one global
-// queue in stage-major order; each resident block takes the next item, waits
-// until the item's predecessor stage has finished all its tiles, runs the
-// tile, and counts it as done.  Every item's predecessors precede it in the
+// ------------------------------------------------------------ persistent launches
+// Several steps (of one or of many compressions) in one persistent launch.
+// Every (instance, step) pair is a stage.  Work items (tiles) sit in one
+// global queue in stage order; each resident block takes the next item, waits
+// until the item's dependencies are met, runs the tile, and counts it.  A
+// dependency is a counter reaching a value: counters count finished tiles per
+// stage and per task, so a tile can wait for a whole stage (S2S waits for the
+// upward pass) or only for the tasks whose rows it reads (a node's N2S waits
+// for its two children, a child's S2N for its parent).  Counters and the
+// queue head only grow: a launch made after `epoch` earlier launches with the
+// same tables waits for epoch * (tiles per launch) + need, so nothing has to
+// be cleared between launches.  Every item's dependencies precede it in the
 // queue and are held by running blocks, so the waits always end; a spin limit
-// still bounds each wait (the block then flags an error and skips the tile).
+// still bounds each wait (the block then flags an error and skips the tile,
+// which still counts as finished).
 struct BInst {
   const TaskDesc* tasks;
   const int* rows;
@@ -429,67 +462,82 @@ struct BInst {
   int vec;
 };
 
-struct BItem { int inst, stage, task, tile; };   // tile = row tile << 16 | column tile
+struct BItem {
+  int inst, stage, task, tile;   // tile = row tile << 16 | column tile
+  int tctr;                      // the task's counter (the stage's counter is `stage`)
+  int dep[2];                    // counters waited for (-1: none)
+  int need[2];                   // finished tiles they must reach in this launch
+};
 
 struct BArgs {
-  const BInst* inst;
+  const BInst* inst;             // per instance, or nullptr: every item uses `one`
+  BInst one;
   const BItem* items;
   int n_items;
-  const int* stage_prev;    // predecessor stage or -1
-  const int* stage_need;    // tiles of the predecessor stage
-  const int* stage_acc;     // 1: the stage accumulates into its output
-  int* done;                // per stage: finished tiles (zero at launch)
-  int* head;                // queue head (zero at launch)
-  int* error;               // set to 1 if a wait exceeded the spin limit
+  const int* stage_acc;          // 1: the stage accumulates into its output
+  const int* ctr_total;          // tiles each counter receives per launch
+  unsigned long long* ctr;       // stage counters, then task counters
+  unsigned long long* head;      // queue head
+  unsigned long long head_base;  // head value when this launch starts
+  unsigned long long epoch;      // earlier launches with these counters
+  int* error;                    // set to 1 if a wait exceeded the spin limit
   long long spin_limit;
 };
 
 template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
-__global__ __launch_bounds__(NT) void batched_tiles(BArgs b) {
+__device__ __forceinline__ void persistent_tiles(const BArgs& b) {
   __shared__ Smem<PREC, BM, BN> sm;
   __shared__ int s_item;
   __shared__ int s_ok;
   // Lane 0's bookkeeping (publish the previous tile, take the next item, wait
-  // for the item's predecessor stage) sits at the top of the iteration, each
-  // part closed by a barrier, and the values it broadcasts are made
-  // wave-uniform with readfirstlane: the loop's exit and back edge are then
-  // uniform branches, so the compiler cannot split lane 0 from its wave.
-  int last_stage = -1;
+  // for the item's dependencies) sits at the top of the iteration, each part
+  // closed by a barrier, and the values it broadcasts are made wave-uniform
+  // with readfirstlane: the loop's exit and back edge are then uniform
+  // branches, so the compiler cannot split lane 0 from its wave.
+  int last_s = -1, last_t = -1;
   while (true) {
     if (threadIdx.x == 0) {
-      if (last_stage >= 0)
-        __hip_atomic_fetch_add(&b.done[last_stage], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      s_item = atomicAdd(b.head, 1);
+      if (last_s >= 0) {
+        // the tile's rows were written with device-coherent stores that every
+        // thread waited for before the barrier: relaxed increments publish it
+        __hip_atomic_fetch_add(&b.ctr[last_s], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&b.ctr[last_t], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      const unsigned long long h = atomicAdd(b.head, 1ull) - b.head_base;
+      s_item = h < (unsigned long long)b.n_items ? (int)h : b.n_items;
     }
     __syncthreads();
     const int idx = __builtin_amdgcn_readfirstlane(s_item);
     if (idx >= b.n_items) break;
     const BItem it = b.items[idx];
-    const int stage = __builtin_amdgcn_readfirstlane(it.stage);
     if (threadIdx.x == 0) {
       int ok = 1;
-      const int prev = b.stage_prev[stage];
-      if (prev >= 0) {
-        // Poll with relaxed loads (an acquire on every poll would invalidate
-        // the L2 each time and starve the blocks doing the work), then one
-        // acquire fence once the predecessor stage is complete.
-        const int need = b.stage_need[stage];
-        long long polls = 0;
-        while (__hip_atomic_load(&b.done[prev], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-          __builtin_amdgcn_s_sleep(8);
-          if (++polls > b.spin_limit) {
-            atomicExch(b.error, 1);
-            ok = 0;
-            break;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const int c = it.dep[d];
+        if (c >= 0 && ok) {
+          // Relaxed polls, and no acquire fence after them: the rows this tile
+          // reads from other tiles are loaded with device-coherent loads (an
+          // acquire at device scope would invalidate this XCD's L2 and cost
+          // every block on it its cached operands).
+          const unsigned long long target = b.epoch * (unsigned long long)b.ctr_total[c] + (unsigned long long)it.need[d];
+          long long polls = 0;
+          while (__hip_atomic_load(&b.ctr[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(8);
+            if (++polls > b.spin_limit) {
+              atomicExch(b.error, 1);
+              ok = 0;
+              break;
+            }
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       s_ok = ok;
     }
     __syncthreads();
+    const int stage = __builtin_amdgcn_readfirstlane(it.stage);
     if (__builtin_amdgcn_readfirstlane(s_ok)) {
-      const BInst& in = b.inst[__builtin_amdgcn_readfirstlane(it.inst)];
+      const BInst& in = b.inst ? b.inst[__builtin_amdgcn_readfirstlane(it.inst)] : b.one;
       KArgs a;
       a.tasks = in.tasks;
       a.items = nullptr;
@@ -507,12 +555,22 @@ __global__ __launch_bounds__(NT) void batched_tiles(BArgs b) {
       const TaskDesc td = in.tasks[__builtin_amdgcn_readfirstlane(it.task)];
       const int tile = __builtin_amdgcn_readfirstlane(it.tile);
       const int m0 = (tile >> 16) * BM, n0 = (tile & 0xffff) * BN;
-      tile_body<PREC, BM, BN, WM, WN, VEC>(a, td, m0, n0, b.stage_acc[stage] != 0, sm);
+      tile_body<PREC, BM, BN, WM, WN, VEC, true>(a, td, m0, n0, b.stage_acc[stage] != 0, sm);
     }
-    last_stage = stage;
-    __syncthreads();                      // every thread's stores issued, LDS free
+    last_s = stage;
+    last_t = __builtin_amdgcn_readfirstlane(it.tctr);
+    __builtin_amdgcn_s_waitcnt(0);        // this thread's stores have completed
+    __syncthreads();                      // every thread's stores done, LDS free
   }
 }
+
+// Many compressions in one launch (all steps of each), and the tree passes of
+// one compression (entry points with the same body, so profiles separate
+// them).
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
+__global__ __launch_bounds__(NT) void batched_tiles(BArgs b) { persistent_tiles<PREC, BM, BN, WM, WN, VEC>(b); }
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
+__global__ __launch_bounds__(NT) void pass_tiles(BArgs b) { persistent_tiles<PREC, BM, BN, WM, WN, VEC>(b); }
 
 typedef void (*BatchedFn)(BArgs);
 constexpr int kNumCfg = 8;
@@ -523,7 +581,8 @@ constexpr Cfg kCfgs[kNumCfg] = {{128, 128}, {128, 64}, {64, 128}, {64, 64},
 
 template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
 void fill_family(KernelFn* row, BatchedFn* brow) {
-  *brow = batched_tiles<PREC, BM, BN, WM, WN, VEC>;
+  brow[0] = batched_tiles<PREC, BM, BN, WM, WN, VEC>;
+  brow[1] = pass_tiles<PREC, BM, BN, WM, WN, VEC>;
   row[0] = n2s_tiles<PREC, BM, BN, WM, WN, VEC>;
   row[1] = s2s_tiles<PREC, BM, BN, WM, WN, VEC>;
   row[2] = s2n_tiles<PREC, BM, BN, WM, WN, VEC>;
@@ -531,17 +590,17 @@ void fill_family(KernelFn* row, BatchedFn* brow) {
   row[4] = leaf_tiles<PREC, BM, BN, WM, WN, true, VEC>;
 }
 
-// table[cfg * kNumFamily + family], batched[cfg]
+// table[cfg * kNumFamily + family], persistent[cfg * 2 + (0 batched, 1 pass)]
 template <int PREC, bool VEC>
-void fill_table(KernelFn* table, BatchedFn* batched) {
-  fill_family<PREC, 128, 128, 2, 2, VEC>(table + 0 * kNumFamily, batched + 0);
-  fill_family<PREC, 128, 64, 2, 2, VEC>(table + 1 * kNumFamily, batched + 1);
-  fill_family<PREC, 64, 128, 2, 2, VEC>(table + 2 * kNumFamily, batched + 2);
-  fill_family<PREC, 64, 64, 2, 2, VEC>(table + 3 * kNumFamily, batched + 3);
-  fill_family<PREC, 128, 32, 4, 1, VEC>(table + 4 * kNumFamily, batched + 4);
-  fill_family<PREC, 32, 128, 1, 4, VEC>(table + 5 * kNumFamily, batched + 5);
-  fill_family<PREC, 256, 128, 4, 1, VEC>(table + 6 * kNumFamily, batched + 6);
-  fill_family<PREC, 128, 256, 2, 2, VEC>(table + 7 * kNumFamily, batched + 7);
+void fill_table(KernelFn* table, BatchedFn* persistent) {
+  fill_family<PREC, 128, 128, 2, 2, VEC>(table + 0 * kNumFamily, persistent + 0);
+  fill_family<PREC, 128, 64, 2, 2, VEC>(table + 1 * kNumFamily, persistent + 2);
+  fill_family<PREC, 64, 128, 2, 2, VEC>(table + 2 * kNumFamily, persistent + 4);
+  fill_family<PREC, 64, 64, 2, 2, VEC>(table + 3 * kNumFamily, persistent + 6);
+  fill_family<PREC, 128, 32, 4, 1, VEC>(table + 4 * kNumFamily, persistent + 8);
+  fill_family<PREC, 32, 128, 1, 4, VEC>(table + 5 * kNumFamily, persistent + 10);
+  fill_family<PREC, 256, 128, 4, 1, VEC>(table + 6 * kNumFamily, persistent + 12);
+  fill_family<PREC, 128, 256, 2, 2, VEC>(table + 7 * kNumFamily, persistent + 14);
 }
 
 // One translation unit per (precision, row alignment).

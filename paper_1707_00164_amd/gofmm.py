@@ -77,6 +77,7 @@ SIGNATURES = [
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_void_p]),
     ("gofmm_batched_status", C.c_int, [C.POINTER(C.c_int32)]),
     ("gofmm_batched_spin_limit", C.c_int, [C.c_int64]),
+    ("gofmm_evaluate_status", C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     ("gofmm_launch_count", C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     ("gofmm_launch_info", C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_int64)]),
@@ -248,6 +249,12 @@ class Compression:
             _check(lib().gofmm_launch_info(self.h, i, buf, 64, C.byref(f), C.byref(b)))
             out.append((buf.value.decode(), f.value, b.value))
         return out
+
+    def status(self) -> int:
+        """1 if a dependency wait of this compression's tree passes gave up (waits for the device)."""
+        f = C.c_int32()
+        _check(lib().gofmm_evaluate_status(self.h, C.byref(f)))
+        return f.value
 
     def profile(self, enable: bool, launch: int | None = None):
         """Per-launch HIP-event timing: off, every launch, or only `launch`."""

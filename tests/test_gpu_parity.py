@@ -210,3 +210,71 @@ def test_every_tile_shape(torch, storage, monkeypatch):
         _check(outs[-1], ref, tol=tol, tol_elem=tol_e, what=f"tile {t} {storage}")
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])          # fixed k order: identical whatever the tile shape
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16x3"])
+def test_persistent_passes_match_separate_launches(torch, storage, monkeypatch):
+    """The upward and downward passes run as one persistent launch each, whose
+    tiles wait for the tiles they read; the result equals the one with every
+    launch on its own, bit for bit, over repeated evaluates (the pass counters
+    only grow), and no dependency wait gives up."""
+    import paper_1707_00164_amd as g
+    prec = {"fp32": g.FP32, "bf16x3": g.BF16X3}[storage]
+    rng = np.random.default_rng(11)
+    n = 6000
+    pts = rng.random((n, 4))
+    S = _sampler(pts, "gaussian", 0.4, 1e-3)
+    comp = g.Compression.compress(S, leaf_size=96, max_rank=64, tol=1e-6, kappa=16, budget=0.05, seed=3,
+                                  storage=prec, near_storage=prec)
+    log(f"case persistent passes {storage}: depth {comp.stats().depth}, launches {len(comp.launches())}")
+    W64, Wd = cuda_rhs(n, 40, 5)
+    monkeypatch.setenv("GOFMM_PASSES", "0")
+    ref = comp.evaluate(Wd)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    monkeypatch.setenv("GOFMM_PASSES", "1")
+    U = torch.empty_like(Wd)
+    for rep in range(4):
+        comp.evaluate(Wd, U)
+        torch.cuda.synchronize()
+        assert np.array_equal(U.cpu().numpy(), ref), rep
+    comp.autotune(Wd, U)
+    for rep in range(2):
+        comp.evaluate(Wd, U)
+        torch.cuda.synchronize()
+        assert np.array_equal(U.cpu().numpy(), ref), rep
+    assert comp.status() == 0
+    K = kernels.KernelMatrix(pts, "gaussian", 0.4, 1e-3)
+    rows = workloads.sample_rows(n, 200, 1)
+    want = evaluate.tree_walk(export_read(comp), K, Wd.cpu().numpy().astype(np.float64), rows)
+    tol = TOL if storage == "fp32" else TOL_X3_F
+    assert rel_err(ref[rows], want) <= tol
+
+
+def test_pass_wait_limit_flags_error_and_exits(torch, monkeypatch):
+    """A one-poll bound makes the passes' dependency waits give up: the launch
+    still ends and the status reports it; the default bound restores the
+    exact result."""
+    import paper_1707_00164_amd as g
+    monkeypatch.setenv("GOFMM_PASSES", "1")
+    rng = np.random.default_rng(12)
+    n = 8000
+    pts = rng.random((n, 3))
+    comp = g.Compression.compress(_sampler(pts, "gaussian", 0.4, 1e-3), leaf_size=64, max_rank=48, tol=1e-6,
+                                  kappa=16, budget=0.05, seed=4)
+    W64, Wd = cuda_rhs(n, 32, 6)
+    ref = comp.evaluate(Wd)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    assert comp.status() == 0
+    g.batched_spin_limit(1)
+    try:
+        comp.evaluate(Wd)
+        torch.cuda.synchronize()
+        assert comp.status() == 1
+    finally:
+        g.batched_spin_limit(0)
+    U = comp.evaluate(Wd)
+    torch.cuda.synchronize()
+    assert comp.status() == 0
+    assert np.array_equal(U.cpu().numpy(), ref)
