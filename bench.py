@@ -316,65 +316,93 @@ def form_large(args):
 
 
 def form_serving(args):
-    """Resident compressions, Poisson requests with r uniform in [1, 512]."""
+    """Resident compressions (N log-spaced over 16384 .. 262144, kernels
+    cycling through the three workload families), Poisson requests with r
+    uniform in [1, 512]: saturation throughput, then p50/p99 latency at 50% and
+    90% of it, for every precision form in --precisions (same structures)."""
     import numpy as np
+    import tempfile
     import torch
     import workloads
     import paper_1707_00164_amd as g
-    ws = [w for w in workloads.serving_instances(args.instances) if w.n <= args.max_n]
-    comps = []
+    ws = [w for w in workloads.serving_instances(args.models) if w.n <= args.max_n]
+    base, samplers = [], []
     t0 = time.perf_counter()
     for w in ws:
         pts = workloads.points(w)
         S = g.KernelSampler(pts, w.kernel, w.h, w.shift)
-        comps.append(g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol,
-                                            kappa=w.kappa, budget=w.budget, seed=w.seed))
+        samplers.append(S)
+        base.append(g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol,
+                                           kappa=w.kappa, budget=w.budget, seed=w.seed))
     t_comp = time.perf_counter() - t0
     log(f"compressed {len(ws)} models in {t_comp:.1f} s")
+    paths = []
+    for c in base:
+        fd, path = tempfile.mkstemp(suffix=".gofmm")
+        os.close(fd)
+        c.export(path)
+        paths.append(path)
     rmax = 512
-    srv = g.Server(hbm_budget_bytes=args.hbm_gb << 30, streams=args.streams, max_batch=len(ws))
-    ids = [srv.add(c, rmax) for c in comps]
     rng = np.random.default_rng(7)
     pool = {}
     for i, w in enumerate(ws):       # a few resident input blocks per model
         pool[i] = [torch.from_numpy(workloads.rhs(w.n, rmax, w.seed + k).astype(np.float32)).cuda()
                    for k in range(2)]
     torch.cuda.synchronize()
+    results = {}
+    for name in args.precisions:
+        if name == "bf16":
+            continue                                      # not an equal-accuracy form
+        prec = {"fp32": g.FP32, "bf16x3": g.BF16X3}[name]
+        comps = base if name == "fp32" else [g.Compression.load(p, S, storage=prec, near_storage=prec)
+                                             for p, S in zip(paths, samplers)]
+        need = sum(c.footprint(rmax) + 2 * c.n * rmax * 4 for c in comps)
+        if need + (1 << 30) > args.hbm_gb << 30:
+            raise SystemExit(f"{name}: the models need {need / 2 ** 30:.1f} GiB of HBM, over --hbm-gb")
+        budget = need + (1 << 30)
+        srv = g.Server(hbm_budget_bytes=budget, streams=args.streams, max_batch=len(ws))
+        ids = [srv.add(c, rmax) for c in comps]
+        log(f"{name}: {len(ids)} models resident, {need / 2 ** 30:.1f} GiB")
 
-    def run(n_req, qps):
-        srv.reset_stats()
-        hs = []
-        outs = []
-        t_next = time.perf_counter()
-        for q in range(n_req):
-            i = int(rng.integers(0, len(ws)))
-            r = int(rng.integers(1, rmax + 1))
-            W = pool[i][q % 2][:, :r]
-            U = torch.empty((ws[i].n, r), device="cuda")
-            if qps:
-                t_next += rng.exponential(1.0 / qps)
-                while time.perf_counter() < t_next:
-                    pass
-            hs.append(srv.submit(ids[i], W, U))
-            outs.append(U)
-        for h in hs:
-            srv.wait(h, timeout_ms=120000)
-        st = srv.stats()
-        return {"requests": n_req, "qps_offered": qps, "throughput_rps": round(st.completed / (st.elapsed_ms / 1e3), 1),
-                "columns_per_s": round(st.columns / (st.elapsed_ms / 1e3), 1), "p50_ms": round(st.p50_ms, 3),
-                "p99_ms": round(st.p99_ms, 3), "mean_ms": round(st.mean_ms, 3), "batches": st.batches,
-                "failed": st.failed}
-    run(64, 0)                                     # warm-up (autotune-free path)
-    sat = run(args.requests, 0)                    # burst: saturation throughput
-    log(f"saturation: {sat}")
-    res = {"saturation": sat}
-    for frac in (0.5, 0.9):
-        res[f"poisson_{int(frac * 100)}pct"] = run(args.requests, frac * sat["throughput_rps"])
-        log(f"poisson {frac}: {res[f'poisson_{int(frac * 100)}pct']}")
-    srv.close()
+        def run(n_req, qps):
+            srv.reset_stats()
+            hs = []
+            t_next = time.perf_counter()
+            for q in range(n_req):
+                i = int(rng.integers(0, len(ws)))
+                r = int(rng.integers(1, rmax + 1))
+                W = pool[i][q % 2][:, :r]
+                U = torch.empty((ws[i].n, r), device="cuda")
+                if qps:
+                    t_next += rng.exponential(1.0 / qps)
+                    while time.perf_counter() < t_next:
+                        pass
+                hs.append((srv.submit(ids[i], W, U), U))
+            for h, _ in hs:
+                srv.wait(h, timeout_ms=120000)
+            st = srv.stats()
+            return {"requests": n_req, "qps_offered": round(qps, 1) if qps else None,
+                    "throughput_rps": round(st.completed / (st.elapsed_ms / 1e3), 1),
+                    "columns_per_s": round(st.columns / (st.elapsed_ms / 1e3), 1),
+                    "p50_ms": round(st.p50_ms, 3), "p99_ms": round(st.p99_ms, 3), "mean_ms": round(st.mean_ms, 3),
+                    "batches": st.batches, "failed": st.failed}
+        run(64, 0)                                 # warm-up
+        sat = run(args.requests, 0)                # burst: saturation throughput
+        res = {"hbm_budget_gb": round(budget / 2 ** 30, 1), "saturation": sat}
+        log(f"{name} saturation: {sat}")
+        for frac in (0.5, 0.9):
+            res[f"poisson_{int(frac * 100)}pct"] = run(args.requests, frac * sat["throughput_rps"])
+            log(f"{name} poisson {frac}: {res[f'poisson_{int(frac * 100)}pct']}")
+        srv.close()
+        results[name] = res
+        for c in comps:
+            c.free()
+        torch.cuda.empty_cache()
+    for p in paths:
+        os.unlink(p)
     out = {"metric": METRIC, "form": "serving", "unit": "ms", "n_gpus": 1, "data": "synthetic",
            "config": {"models": len(ws), "n": [w.n for w in ws], "r": "uniform 1..512", "streams": args.streams},
-           "compress_seconds": round(t_comp, 1), "results": res}
+           "compress_seconds": round(t_comp, 1), "results": results}
     print(json.dumps(out), flush=True)
 
 
@@ -402,10 +430,11 @@ def main():
     ap.add_argument("--form", default="flat", choices=["flat", "batched", "serving", "large", "copy"],
                     help="flat: the N=65536 workload (default); batched: 48 compressions in one launch; "
                          "serving: request loop with p50/p99; large: N=262144 in three precisions")
-    ap.add_argument("--instances", type=int, default=48)
+    ap.add_argument("--instances", type=int, default=48, help="batched form: compressions")
+    ap.add_argument("--models", type=int, default=16, help="serving form: resident compressions")
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--streams", type=int, default=2)
-    ap.add_argument("--hbm-gb", type=int, default=64)
+    ap.add_argument("--hbm-gb", type=int, default=240)
     ap.add_argument("--max-n", type=int, default=262144)
     ap.add_argument("--r-list", type=int, nargs="+", default=[1024, 2048])
     ap.add_argument("--precisions", nargs="+", default=["fp32", "bf16", "bf16x3"])
