@@ -240,7 +240,15 @@ static std::pair<int2*, int> items_for(Compression& c, int li, int cfg, int ntn)
   return d->items[key];
 }
 
-// Padded-work model: tile count x tile area x k, plus a per-tile overhead.
+// Cost of one tile in the padded-work model: matrix-core work (weighted by
+// the precision: split BF16 issues three BF16 products, which together are
+// still cheaper than one FP32 product), operand staging (A and B slabs of the
+// tile) and a fixed per-tile latency.
+static double tile_cost(const Cfg& g, int prec, double lda) {
+  const double w = prec == PREC_F32 ? 1.0 : prec == PREC_BF16X3 ? 1.0 / 3.0 : 1.0 / 8.0;
+  return g.bm * g.bn * lda * w + 24.0 * (g.bm + g.bn) * lda + 32.0 * 128 * 128;
+}
+
 static int choose_cfg(const Compression& c, int li, i64 r) {
   const LaunchDesc& l = c.plan.launches[li];
   double best = 1e300;
@@ -252,11 +260,11 @@ static int choose_cfg(const Compression& c, int li, i64 r) {
     for (i32 k = l.t_begin; k < l.t_end; ++k) {
       const TaskDesc& t = c.plan.tasks[k];
       const double mt = (double)((t.m + g.bm - 1) / g.bm);
-      cost += mt * nt * g.bm * g.bn * (double)std::max(t.lda, 32);
+      cost += mt * nt * tile_cost(g, l.prec, (double)std::max(t.lda, 32));
       tiles += mt * nt;
     }
     const double fill = std::min(1.0, tiles / 256.0);
-    cost = cost / fill + tiles * 32.0 * 128 * 128;
+    cost = cost / fill;
     if (cost < best) { best = cost; bc = q; }
   }
   return bc;
@@ -768,8 +776,11 @@ static int batch_cfg_model(int k, Compression* const* c, const i64* r) {
     double cost = 0.0;
     for (int i = 0; i < k; ++i) {
       const double nt = (double)((r[i] + g.bn - 1) / g.bn);
-      for (const TaskDesc& t : c[i]->plan.tasks)
-        cost += (double)((t.m + g.bm - 1) / g.bm) * nt * (g.bm * g.bn * (double)std::max(t.lda, 32) + 32.0 * 128 * 128);
+      for (const LaunchDesc& l : c[i]->plan.launches)
+        for (i32 t = l.t_begin; t < l.t_end; ++t) {
+          const TaskDesc& td = c[i]->plan.tasks[t];
+          cost += (double)((td.m + g.bm - 1) / g.bm) * nt * tile_cost(g, l.prec, (double)std::max(td.lda, 32));
+        }
     }
     if (cost < best) { best = cost; bc = q; }
   }

@@ -69,7 +69,8 @@ struct TaskDesc {
   i64 a_off;    // element offset of A in its buffer, in matrix-core fragment
                 // order (rows padded to 32, k to lda), see the packing
   i64 idx_off;  // offset into the row-code array
-  i32 m, k, lda, node;
+  i32 m, k, lda;
+  i32 kws;      // leading B rows that are workspace rows (the rest are rows of W)
 };
 
 // Row codes: c >= 0 is row c of the caller's W (reads) or U (writes);

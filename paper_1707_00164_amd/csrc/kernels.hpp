@@ -201,7 +201,10 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   // coded ROW_ZERO, columns past r) come from the zero bytes above.  Nothing
   // waits for a B load before the slab is stored to LDS a slab later, and the
   // k loop stays free of branches.
-  auto bload = [&]() {
+  // coh: the slab holds workspace rows (produced by other tiles of a
+  // persistent launch), read with device-coherent loads; rows of W are
+  // read-only during a launch and take the cached path
+  auto bload = [&](bool coh) {
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
       const int sub = tid + t * NT;
@@ -224,7 +227,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
           unsigned long long pa = (unsigned long long)(rowp(e, zr) + col);
           asm volatile("" : "+v"(pa));
           const auto q = (zr || zc) ? Zg : (const __attribute__((address_space(1))) float*)pa;
-          if constexpr (COH) {
+          if (COH && coh) {
             typedef unsigned long long u64 __attribute__((address_space(1)));
             const unsigned long long lo = __hip_atomic_load((u64*)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned long long hi = __hip_atomic_load((u64*)q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -244,7 +247,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const auto x = (zr || col + q >= a.r) ? Zg : p + q;
-            if constexpr (COH)
+            if (COH && coh)
               rbv[t][e][q] = __hip_atomic_load((__attribute__((address_space(1))) float*)x, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
             else
@@ -345,12 +348,12 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   const int ns = td.lda / KSLAB;                     // k is padded to whole slabs
   if (ns > 0) {
     cload(0);
-    bload();
+    bload(0 < td.kws);
     cload(KSLAB);
 #pragma unroll
     for (int s = 0; s < NS; ++s) aload(s, s);
     bstore(0, 0, 4);
-    bload();
+    bload(KSLAB < td.kws);
     cload(2 * KSLAB);
   }
   __syncthreads();
@@ -368,7 +371,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       if (s == 0) bstore(buf ^ 1, 0, 2);
       if (s == 1) {
         bstore(buf ^ 1, 2, 4);
-        bload();
+        bload((kt + 2) * KSLAB < td.kws);
         cload((kt + 3) * KSLAB);
       }
       // one matrix-core instruction at a time, with the step's LDS traffic,

@@ -238,7 +238,11 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
     td.m = (i32)d.m;
     td.k = (i32)k;
     td.lda = (i32)lda;
-    td.node = 0;
+    td.kws = 0;
+    for (i32 code : d.brow) {
+      if (code >= 0) break;
+      ++td.kws;
+    }
     td.a_off = off[d.prec];
     td.idx_off = roff;
     off[d.prec] += rows_stored(d.m) * lda;
