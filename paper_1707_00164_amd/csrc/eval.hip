@@ -498,7 +498,7 @@ static int persistent_cap(int prec, int cfg, int which) {
   if (it != cache.end()) return it->second;
   int per_cu = 0, cus = 0, devid = 0;
   HIP_OK(hipGetDevice(&devid));
-  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tables().b[1][prec][cfg * 2 + which], dev::NT, 0));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tables().b[1][prec][cfg * 2 + which], kCfgs[cfg].nt, 0));
   HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devid));
   const int cap = std::max(1, per_cu) * std::max(1, cus);
   cache[{prec, cfg, which}] = cap;
@@ -597,7 +597,7 @@ static void launch_pass(Compression& c, const Seg& sg, int cfg, const EvalArgs& 
   a.epoch = P.epoch;
   a.error = P.error;
   a.spin_limit = spin_limit_ref();
-  hipLaunchKernelGGL(tables().b[a.one.vec ? 1 : 0][prec][cfg * 2 + 1], dim3(P.grid), dim3(dev::NT), 0, e.stream, a);
+  hipLaunchKernelGGL(tables().b[a.one.vec ? 1 : 0][prec][cfg * 2 + 1], dim3(P.grid), dim3(kCfgs[cfg].nt), 0, e.stream, a);
   HIP_OK(hipGetLastError());
   P.epoch += 1;
   P.head_base += (unsigned long long)P.n_items + (unsigned long long)P.grid;
@@ -624,7 +624,7 @@ static void launch_seg(Compression& c, const Seg& sg, int cfg, const EvalArgs& e
     if (lo.kind == 6) lo.kind = 1;
     lo.accumulate = 0;
   }
-  hipLaunchKernelGGL(kernel_for(lo, cfg, a.vec != 0), dim3(grid), dim3(dev::NT), 0, e.stream, a);
+  hipLaunchKernelGGL(kernel_for(lo, cfg, a.vec != 0), dim3(grid), dim3(kCfgs[cfg].nt), 0, e.stream, a);
   HIP_OK(hipGetLastError());
 }
 
@@ -687,8 +687,8 @@ void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
       HIP_OK(hipEventElapsedTime(&ms, e0, e1));
       if (ms < best) { best = ms; bc = q; }
       if (std::getenv("GOFMM_TUNE_LOG"))
-        std::fprintf(stderr, "tune %s%s r=%lld cfg %dx%d: %.4f ms\n", c.plan.launches[sg.j0].name.c_str(),
-                     sg.pass ? " (pass)" : "", (long long)r, kCfgs[q].bm, kCfgs[q].bn, ms / reps);
+        std::fprintf(stderr, "tune %s%s r=%lld cfg %dx%dx%d: %.4f ms\n", c.plan.launches[sg.j0].name.c_str(),
+                     sg.pass ? " (pass)" : "", (long long)r, kCfgs[q].bm, kCfgs[q].bn, kCfgs[q].nt, ms / reps);
     }
     c.dev->tuned[{sg.pass ? -(sg.j0 + 1) : sg.j0, r}] = bc;
   }
@@ -867,7 +867,7 @@ void ring_launch(BatchRing& ring, int k, Compression* const* c, const i64* r, co
     a.error = reinterpret_cast<int*>(dv + o_err);
     a.spin_limit = spin_limit_ref();
     const int grid = std::max(1, std::min(a.n_items, persistent_cap(prec, cfg, 0)));
-    hipLaunchKernelGGL(tables().b[all_vec ? 1 : 0][prec][cfg * 2], dim3(grid), dim3(dev::NT), 0, st, a);
+    hipLaunchKernelGGL(tables().b[all_vec ? 1 : 0][prec][cfg * 2], dim3(grid), dim3(kCfgs[cfg].nt), 0, st, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(h + o_err, dv + o_err, sizeof(int), hipMemcpyDeviceToHost, st));
   }
@@ -948,7 +948,7 @@ void device_autotune_batched(int k, Compression* const* c, const i64* r, const f
       float ms = 0.f;
       HIP_OK(hipEventElapsedTime(&ms, e0, e1));
       if (std::getenv("GOFMM_TUNE_LOG"))
-        std::fprintf(stderr, "tune batched k=%d cfg %dx%d: %.4f ms\n", k, kCfgs[q].bm, kCfgs[q].bn, ms / reps);
+        std::fprintf(stderr, "tune batched k=%d cfg %dx%dx%d: %.4f ms\n", k, kCfgs[q].bm, kCfgs[q].bn, kCfgs[q].nt, ms / reps);
       if (ms < best) { best = ms; bc = q; }
     }
     (void)hipEventDestroy(e0);

@@ -46,7 +46,6 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int NT = 256;
 
 struct KArgs {
   const TaskDesc* tasks;
@@ -145,7 +144,8 @@ template <int PREC, int BM, int BN, int WM, int WN, bool VEC, bool COH = false>
 __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, int m0, int n0, bool accumulate,
                                           Smem<PREC, BM, BN>& sm) {
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 32, TN = WTN / 32;
-  static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "tile shape");
+  constexpr int NT = WM * WN * 64;                   // threads per block (4 or 8 waves)
+  static_assert((WM * WN == 4 || WM * WN == 8) && TM >= 1 && TN >= 1, "tile shape");
   constexpr bool F32 = PREC == PREC_F32;
   constexpr bool X3 = PREC == PREC_BF16X3;
   constexpr int NPL = X3 ? 2 : 1;                    // planes per operand
@@ -182,8 +182,11 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
 
   // B: sub-blocks of SBR rows x 4 columns per thread and slab.  Codes of slabs
   // past the end are clamped to the last k of the block: the rows they fetch
-  // only reach LDS buffers that are never read again.
+  // only reach LDS buffers that are never read again.  With more threads than
+  // sub-blocks, whole waves sit out the B staging.
   constexpr int BSUB = (KSLAB / SBR) * (BN / 4), BST = (BSUB + NT - 1) / NT;
+  static_assert(BSUB % 64 == 0, "sub-blocks per wave");
+  const bool bwave = BSUB >= NT || wid * 64 < BSUB;
   int nc[BST][SBR];
   f32x4 rbv[BST][SBR];
   auto cload = [&](int k0) {
@@ -205,6 +208,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   // persistent launch), read with device-coherent loads; rows of W are
   // read-only during a launch and take the cached path
   auto bload = [&](bool coh) {
+    if (!bwave) return;
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
       const int sub = tid + t * NT;
@@ -425,13 +429,13 @@ __device__ __forceinline__ void gemm_tiles(const KArgs& a) {
 // Entry points with the same body, so that profiles separate the upward pass,
 // the far field, the downward pass and the leaf output.
 template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
-__global__ __launch_bounds__(NT) void n2s_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false, VEC>(a); }
+__global__ __launch_bounds__(WM * WN * 64) void n2s_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false, VEC>(a); }
 template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
-__global__ __launch_bounds__(NT) void s2s_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false, VEC>(a); }
+__global__ __launch_bounds__(WM * WN * 64) void s2s_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false, VEC>(a); }
 template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
-__global__ __launch_bounds__(NT) void s2n_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, true, VEC>(a); }
+__global__ __launch_bounds__(WM * WN * 64) void s2n_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, true, VEC>(a); }
 template <int PREC, int BM, int BN, int WM, int WN, bool ACC, bool VEC>
-__global__ __launch_bounds__(NT) void leaf_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, ACC, VEC>(a); }
+__global__ __launch_bounds__(WM * WN * 64) void leaf_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, ACC, VEC>(a); }
 
 typedef void (*KernelFn)(KArgs);
 
@@ -571,16 +575,17 @@ __device__ __forceinline__ void persistent_tiles(const BArgs& b) {
 // one compression (entry points with the same body, so profiles separate
 // them).
 template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
-__global__ __launch_bounds__(NT) void batched_tiles(BArgs b) { persistent_tiles<PREC, BM, BN, WM, WN, VEC>(b); }
+__global__ __launch_bounds__(WM * WN * 64) void batched_tiles(BArgs b) { persistent_tiles<PREC, BM, BN, WM, WN, VEC>(b); }
 template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
-__global__ __launch_bounds__(NT) void pass_tiles(BArgs b) { persistent_tiles<PREC, BM, BN, WM, WN, VEC>(b); }
+__global__ __launch_bounds__(WM * WN * 64) void pass_tiles(BArgs b) { persistent_tiles<PREC, BM, BN, WM, WN, VEC>(b); }
 
 typedef void (*BatchedFn)(BArgs);
-constexpr int kNumCfg = 8;
+constexpr int kNumCfg = 10;
 constexpr int kNumFamily = 5;   // n2s, s2s, s2n (accumulate), leaf, leaf accumulating
-struct Cfg { int bm, bn; };
-constexpr Cfg kCfgs[kNumCfg] = {{128, 128}, {128, 64}, {64, 128}, {64, 64},
-                                {128, 32}, {32, 128}, {256, 128}, {128, 256}};
+struct Cfg { int bm, bn, nt; };   // tile rows, tile columns, threads per block
+constexpr Cfg kCfgs[kNumCfg] = {{128, 128, 256}, {128, 64, 256}, {64, 128, 256}, {64, 64, 256},
+                                {128, 32, 256},  {32, 128, 256}, {256, 128, 256}, {128, 256, 256},
+                                {256, 128, 512}, {128, 256, 512}};
 
 template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
 void fill_family(KernelFn* row, BatchedFn* brow) {
@@ -604,6 +609,9 @@ void fill_table(KernelFn* table, BatchedFn* persistent) {
   fill_family<PREC, 32, 128, 1, 4, VEC>(table + 5 * kNumFamily, persistent + 10);
   fill_family<PREC, 256, 128, 4, 1, VEC>(table + 6 * kNumFamily, persistent + 12);
   fill_family<PREC, 128, 256, 2, 2, VEC>(table + 7 * kNumFamily, persistent + 14);
+  // 8 waves (two per SIMD) over the large tiles, each wave 64 x 64
+  fill_family<PREC, 256, 128, 4, 2, VEC>(table + 8 * kNumFamily, persistent + 16);
+  fill_family<PREC, 128, 256, 2, 4, VEC>(table + 9 * kNumFamily, persistent + 18);
 }
 
 // One translation unit per (precision, row alignment).
