@@ -169,7 +169,11 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   const auto Ab = gmem(reinterpret_cast<const u32x4*>(a.A));
   const long long abase = td.a_off / EPU;            // in 16-byte units
   const long long aplane = a.plane / EPU;
-  u32x4 ra[NS][NPL][TM];
+  // Prefetch depth in slabs: the large BF16 tiles keep two slabs of A and of
+  // B rows in flight (their slabs are short next to memory latency); the
+  // others one.
+  constexpr int DEP = (!F32 && WM * WN == 4 && BM == 256 && BN == 128) ? 2 : 1;
+  u32x4 ra[DEP * NS][NPL][TM];
   auto aload = [&](int slot, int g) {
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
@@ -188,7 +192,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   static_assert(BSUB % 64 == 0, "sub-blocks per wave");
   const bool bwave = BSUB >= NT || wid * 64 < BSUB;
   int nc[BST][SBR];
-  f32x4 rbv[BST][SBR];
+  f32x4 rbv[DEP][BST][SBR];
   auto cload = [&](int k0) {
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
@@ -207,7 +211,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   // coh: the slab holds workspace rows (produced by other tiles of a
   // persistent launch), read with device-coherent loads; rows of W are
   // read-only during a launch and take the cached path
-  auto bload = [&](bool coh) {
+  auto bload = [&](bool coh, int set) {
     if (!bwave) return;
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
@@ -235,10 +239,10 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
             typedef unsigned long long u64 __attribute__((address_space(1)));
             const unsigned long long lo = __hip_atomic_load((u64*)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned long long hi = __hip_atomic_load((u64*)q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            rbv[t][e] = f32x4{__builtin_bit_cast(float, (unsigned int)lo), __builtin_bit_cast(float, (unsigned int)(lo >> 32)),
-                              __builtin_bit_cast(float, (unsigned int)hi), __builtin_bit_cast(float, (unsigned int)(hi >> 32))};
+            rbv[set][t][e] = f32x4{__builtin_bit_cast(float, (unsigned int)lo), __builtin_bit_cast(float, (unsigned int)(lo >> 32)),
+                                   __builtin_bit_cast(float, (unsigned int)hi), __builtin_bit_cast(float, (unsigned int)(hi >> 32))};
           } else {
-            rbv[t][e] = *(const __attribute__((address_space(1))) f32x4*)q;
+            rbv[set][t][e] = *(const __attribute__((address_space(1))) f32x4*)q;
           }
         }
       } else {
@@ -252,17 +256,17 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
           for (int q = 0; q < 4; ++q) {
             const auto x = (zr || col + q >= a.r) ? Zg : p + q;
             if (COH && coh)
-              rbv[t][e][q] = __hip_atomic_load((__attribute__((address_space(1))) float*)x, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+              rbv[set][t][e][q] = __hip_atomic_load((__attribute__((address_space(1))) float*)x, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
             else
-              rbv[t][e][q] = *x;
+              rbv[set][t][e][q] = *x;
           }
         }
       }
     }
   };
-  // columns j0 .. j1-1 of each thread's sub-blocks
-  auto bstore = [&](int buf, int j0, int j1) {
+  // columns j0 .. j1-1 of each thread's sub-blocks, from register set `set`
+  auto bstore = [&](int buf, int j0, int j1, int set) {
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
       const int sub = tid + t * NT;
@@ -272,13 +276,13 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
         for (int j = j0; j < j1; ++j) {
           const int w = swz(4 * cq + j, kq);
           if constexpr (F32) {
-            const f32x4 v = {rbv[t][0][j], rbv[t][1][j], rbv[t][2][j], rbv[t][3][j]};
+            const f32x4 v = {rbv[set][t][0][j], rbv[set][t][1][j], rbv[set][t][2][j], rbv[set][t][3][j]};
             *reinterpret_cast<f32x4*>(&sm.sB[buf][0][w]) = v;
           } else {
             u32x4 hi, lo;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const f32x2 x = {rbv[t][2 * e][j], rbv[t][2 * e + 1][j]};
+              const f32x2 x = {rbv[set][t][2 * e][j], rbv[set][t][2 * e + 1][j]};
               const bf16x2 h = __builtin_convertvector(x, bf16x2);
               hi[e] = __builtin_bit_cast(unsigned int, h);
               if constexpr (X3) {
@@ -312,8 +316,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       for (int p = 0; p < NPL; ++p) bfr[slot][p][j] = *reinterpret_cast<const u32x4*>(&sm.sB[buf][p][w]);
     }
   };
-  auto mfma_step = [&](int s) {
-    const int bs = s & 1;
+  auto mfma_step = [&](int s, int bs) {
     if constexpr (F32) {
       // (whole vectors are reinterpreted before indexing: a bit cast of a
       // single vector element reads element 0 with this compiler)
@@ -350,33 +353,41 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   };
 
   const int ns = td.lda / KSLAB;                     // k is padded to whole slabs
+  // slab j's A fragments sit in ring slots (j % DEP) * NS + step, its B rows
+  // in register set j % DEP
   if (ns > 0) {
     cload(0);
-    bload(0 < td.kws);
-    cload(KSLAB);
+    bload(0 < td.kws, 0);
+    if constexpr (DEP == 2) {
+      cload(KSLAB);
+      bload(KSLAB < td.kws, 1);
+    }
+    cload(DEP * KSLAB);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) aload(s, s);
-    bstore(0, 0, 4);
-    bload(KSLAB < td.kws);
-    cload(2 * KSLAB);
+    for (int s = 0; s < DEP * NS; ++s) aload(s, s);
+    bstore(0, 0, 4, 0);
+    bload(DEP * KSLAB < td.kws, 0);
+    cload((DEP + 1) * KSLAB);
   }
   __syncthreads();
-  for (int kt = 0; kt < ns; ++kt) {
+  auto iter = [&](int kt, auto setc) {
+    constexpr int SET = decltype(setc)::value;       // kt % DEP
+    constexpr int NXT = DEP == 2 ? 1 - SET : 0;      // register set of slabs kt + 1 and kt + 1 + DEP
     const int buf = kt & 1;
     bread(0, buf, 0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if (s + 1 < NS) bread((s + 1) & 1, buf, s + 1);
-      mfma_step(s);
-      aload(s, (kt + 1) * NS + s);
+      mfma_step(SET * NS + s, s & 1);
+      aload(SET * NS + s, (kt + DEP) * NS + s);
       // slab kt + 1 into the other buffer (no wave reads it before the
-      // barrier below), then the B rows of slab kt + 2 and the codes of
-      // slab kt + 3; past the last slab these move data that nobody reads
-      if (s == 0) bstore(buf ^ 1, 0, 2);
+      // barrier below), then the B rows of slab kt + 1 + DEP and the codes of
+      // the slab after; past the last slab these move data that nobody reads
+      if (s == 0) bstore(buf ^ 1, 0, 2, NXT);
       if (s == 1) {
-        bstore(buf ^ 1, 2, 4);
-        bload((kt + 2) * KSLAB < td.kws);
-        cload((kt + 3) * KSLAB);
+        bstore(buf ^ 1, 2, 4, NXT);
+        bload((kt + 1 + DEP) * KSLAB < td.kws, NXT);
+        cload((kt + 2 + DEP) * KSLAB);
       }
       // one matrix-core instruction at a time, with the step's LDS traffic,
       // global loads and vector work placed in its shadow
@@ -384,6 +395,16 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
+  };
+  if constexpr (DEP == 1) {
+    for (int kt = 0; kt < ns; ++kt) iter(kt, std::integral_constant<int, 0>());
+  } else {
+    int kt = 0;
+    for (; kt + 1 < ns; kt += 2) {
+      iter(kt, std::integral_constant<int, 0>());
+      iter(kt + 1, std::integral_constant<int, 1>());
+    }
+    if (kt < ns) iter(kt, std::integral_constant<int, 0>());
   }
 
   // epilogue: accumulator (i, j, v) of lane (li, lh) is row 8(v/4) + 4 lh + v%4,
