@@ -155,7 +155,24 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   constexpr int SBR = F32 ? 4 : 8;                   // B rows per sub-block (one 16-byte LDS chunk)
   const int tid = threadIdx.x;
   const int lane = tid & 63, li = lane & 31, lh = lane >> 5;
-  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wid / WN, wc = wid % WN;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // 8 waves: waves w and w + 4 are placed on one SIMD, so they get
+  // complementary halves of the rows and of the columns; a tile whose last
+  // rows or columns are empty then leaves one busy wave on every SIMD
+  int wr, wc;
+  if constexpr (WM * WN == 8) {
+    const int p = wid & 3, h = wid >> 2;
+    if constexpr (WM == 4) {
+      wr = h ? 3 - (p & 1) : (p & 1);
+      wc = h ? 1 - (p >> 1) : (p >> 1);
+    } else {
+      wr = h;
+      wc = h ? 3 - p : p;
+    }
+  } else {
+    wr = wid / WN;
+    wc = wid % WN;
+  }
   const auto codes = gmem(a.rows + td.idx_off);
   for (int i = tid; i < BM; i += NT) sm.sOut[i] = (m0 + i < td.m) ? codes[td.lda + m0 + i] : ROW_ZERO;
 
@@ -355,6 +372,14 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   const int ns = td.lda / KSLAB;                     // k is padded to whole slabs
   // slab j's A fragments sit in ring slots (j % DEP) * NS + step, its B rows
   // in register set j % DEP
+  // In the 8-wave shapes (two waves per SIMD) a wave whose rows all lie past
+  // the task's m, or whose columns all lie past r, has no products to form:
+  // it still stages its share of B and meets every barrier, but loads no A
+  // and issues no matrix-core work, so its SIMD partner has the matrix cores
+  // to itself.  (The 4-wave shapes keep one k loop: a second copy costs them
+  // registers, and an idle wave there would only leave its SIMD idle.)
+  constexpr bool IDLE = WM * WN == 8;
+  const bool act = !IDLE || __builtin_amdgcn_readfirstlane((rb0 < nrb && n0 + wc * WTN < a.r) ? 1 : 0) != 0;
   if (ns > 0) {
     cload(0);
     bload(0 < td.kws, 0);
@@ -363,23 +388,28 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       bload(KSLAB < td.kws, 1);
     }
     cload(DEP * KSLAB);
+    if (act) {
 #pragma unroll
-    for (int s = 0; s < DEP * NS; ++s) aload(s, s);
+      for (int s = 0; s < DEP * NS; ++s) aload(s, s);
+    }
     bstore(0, 0, 4, 0);
     bload(DEP * KSLAB < td.kws, 0);
     cload((DEP + 1) * KSLAB);
   }
   __syncthreads();
-  auto iter = [&](int kt, auto setc) {
+  auto iter = [&](int kt, auto setc, auto actc) {
     constexpr int SET = decltype(setc)::value;       // kt % DEP
     constexpr int NXT = DEP == 2 ? 1 - SET : 0;      // register set of slabs kt + 1 and kt + 1 + DEP
+    constexpr bool ACT = decltype(actc)::value;
     const int buf = kt & 1;
-    bread(0, buf, 0);
+    if constexpr (ACT) bread(0, buf, 0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      if (s + 1 < NS) bread((s + 1) & 1, buf, s + 1);
-      mfma_step(SET * NS + s, s & 1);
-      aload(SET * NS + s, (kt + DEP) * NS + s);
+      if constexpr (ACT) {
+        if (s + 1 < NS) bread((s + 1) & 1, buf, s + 1);
+        mfma_step(SET * NS + s, s & 1);
+        aload(SET * NS + s, (kt + DEP) * NS + s);
+      }
       // slab kt + 1 into the other buffer (no wave reads it before the
       // barrier below), then the B rows of slab kt + 1 + DEP and the codes of
       // the slab after; past the last slab these move data that nobody reads
@@ -391,20 +421,28 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       }
       // one matrix-core instruction at a time, with the step's LDS traffic,
       // global loads and vector work placed in its shadow
-      if constexpr (F32) interleave<TM * TN * 4, 12>();
+      if constexpr (F32 && ACT) interleave<TM * TN * 4, 12>();
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
   };
-  if constexpr (DEP == 1) {
-    for (int kt = 0; kt < ns; ++kt) iter(kt, std::integral_constant<int, 0>());
-  } else {
-    int kt = 0;
-    for (; kt + 1 < ns; kt += 2) {
-      iter(kt, std::integral_constant<int, 0>());
-      iter(kt + 1, std::integral_constant<int, 1>());
+  auto kloop = [&](auto actc) {
+    if constexpr (DEP == 1) {
+      for (int kt = 0; kt < ns; ++kt) iter(kt, std::integral_constant<int, 0>(), actc);
+    } else {
+      int kt = 0;
+      for (; kt + 1 < ns; kt += 2) {
+        iter(kt, std::integral_constant<int, 0>(), actc);
+        iter(kt + 1, std::integral_constant<int, 1>(), actc);
+      }
+      if (kt < ns) iter(kt, std::integral_constant<int, 0>(), actc);
     }
-    if (kt < ns) iter(kt, std::integral_constant<int, 0>());
+  };
+  if constexpr (!IDLE) {
+    kloop(std::true_type());
+  } else {
+    if (act) kloop(std::true_type());
+    else kloop(std::false_type());
   }
 
   // epilogue: accumulator (i, j, v) of lane (li, lh) is row 8(v/4) + 4 lh + v%4,
