@@ -162,7 +162,10 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   int wr, wc;
   if constexpr (WM * WN == 8) {
     const int p = wid & 3, h = wid >> 2;
-    if constexpr (WM == 4) {
+    if constexpr (WM == 8) {
+      wr = h ? 7 - p : p;
+      wc = 0;
+    } else if constexpr (WM == 4) {
       wr = h ? 3 - (p & 1) : (p & 1);
       wc = h ? 1 - (p >> 1) : (p >> 1);
     } else {
@@ -639,12 +642,12 @@ template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
 __global__ __launch_bounds__(WM * WN * 64) void pass_tiles(BArgs b) { persistent_tiles<PREC, BM, BN, WM, WN, VEC>(b); }
 
 typedef void (*BatchedFn)(BArgs);
-constexpr int kNumCfg = 10;
+constexpr int kNumCfg = 11;
 constexpr int kNumFamily = 5;   // n2s, s2s, s2n (accumulate), leaf, leaf accumulating
 struct Cfg { int bm, bn, nt; };   // tile rows, tile columns, threads per block
 constexpr Cfg kCfgs[kNumCfg] = {{128, 128, 256}, {128, 64, 256}, {64, 128, 256}, {64, 64, 256},
                                 {128, 32, 256},  {32, 128, 256}, {256, 128, 256}, {128, 256, 256},
-                                {256, 128, 512}, {128, 256, 512}};
+                                {256, 128, 512}, {128, 256, 512}, {256, 128, 512}};
 
 template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
 void fill_family(KernelFn* row, BatchedFn* brow) {
@@ -671,6 +674,8 @@ void fill_table(KernelFn* table, BatchedFn* persistent) {
   // 8 waves (two per SIMD) over the large tiles, each wave 64 x 64
   fill_family<PREC, 256, 128, 4, 2, VEC>(table + 8 * kNumFamily, persistent + 16);
   fill_family<PREC, 128, 256, 2, 4, VEC>(table + 9 * kNumFamily, persistent + 18);
+  // 8 waves stacked along the rows, each wave 32 x 128
+  fill_family<PREC, 256, 128, 8, 1, VEC>(table + 10 * kNumFamily, persistent + 20);
 }
 
 // One translation unit per (precision, row alignment).

@@ -201,7 +201,7 @@ def test_every_tile_shape(torch, storage, monkeypatch):
     W64, Wd = cuda_rhs(n, 45, 77)
     ref = evaluate.tree_walk(export_read(comp), K, Wd.cpu().numpy().astype(np.float64))
     outs = []
-    for t in range(10):
+    for t in range(11):                             # every tile shape the library has
         monkeypatch.setenv("GOFMM_TILE", str(t))
         U = comp.evaluate(Wd)
         torch.cuda.synchronize()
