@@ -124,6 +124,27 @@ int gofmm_compress(int64_t n, gofmm_sampler sampler, void* user,
 int gofmm_import(const char* path, gofmm_sampler sampler, void* user,
                  const gofmm_params* params, gofmm_compression** out);
 
+/*
+ * Compute the near-field blocks K(b, a) on the device instead of storing them
+ * (Sec. 2.2: caching the near blocks after compression is optional; Sec. 4,
+ * the memory-limited runs: evaluate them on the fly from the points).
+ * kernel_state must come from gofmm_kernel_create (below) and describe the
+ * matrix c was built from (same n, points in the original order, at most 8
+ * coordinates); the library copies what it needs, so the state may be freed
+ * afterwards.  The plan is rebuilt: P and the coupling blocks are sampled
+ * again through the state (threads <= 0: all host threads), the near blocks
+ * are dropped from the operator, and every evaluate computes them in FP32,
+ * entry by entry from the points (kernel of the squared distance, summed
+ * coordinate by coordinate, plus the shift where the two indices are equal),
+ * inside the L2L launch, whatever near_storage says.  Any device copy of the
+ * compression is released first.  Compressions in this mode cannot be
+ * batched or served (GOFMM_EINVAL there).  Errors: GOFMM_EINVAL for NULL
+ * arguments, a pointer that is not such a state, more than 8 coordinates or a
+ * different n; sampling errors as for gofmm_compress, after which c holds no
+ * operator and can only be freed.
+ */
+int gofmm_use_device_kernel(gofmm_compression* c, void* kernel_state, int32_t threads);
+
 /* Write the structure of a compression (no kernel blocks) to `path`. */
 int gofmm_export(const gofmm_compression* c, const char* path);
 

@@ -115,6 +115,28 @@ extern "C" int gofmm_import(const char* path, gofmm_sampler sampler, void* user,
   });
 }
 
+extern "C" int gofmm_use_device_kernel(gofmm_compression* c, void* kernel_state, int32_t threads) {
+  return guarded([&] {
+    if (!c || !kernel_state) fail(GOFMM_EINVAL, "NULL argument");
+    GeoKernel g;
+    if (!kernel_state_geo(kernel_state, g))
+      fail(GOFMM_EINVAL, "not a gofmm_kernel_create state, or points with more than 8 coordinates");
+    if ((i64)(g.pts.size() / kGeoStride) != c->c.n) fail(GOFMM_EINVAL, "the kernel's point count differs from n");
+    if (c->c.dev) {                   // the plan changes: drop the device copy
+      device_state_free(c->c.dev);
+      c->c.dev = nullptr;
+    }
+    c->c.geo = std::move(g);
+    Sampler K{gofmm_kernel_sample, kernel_state};
+    try {
+      build_plan(c->c, K, threads > 0 ? threads : omp_get_max_threads());
+    } catch (...) {
+      c->c.geo = GeoKernel();
+      throw;
+    }
+  });
+}
+
 extern "C" int gofmm_export(const gofmm_compression* c, const char* path) {
   return guarded([&] {
     if (!c || !path) fail(GOFMM_EINVAL, "NULL argument");
@@ -291,7 +313,8 @@ extern "C" int gofmm_stats(const gofmm_compression* c, gofmm_stats_t* out) {
       out->operator_bytes_phase[p] = x.plan.bytes_phase[p];
     }
     out->operator_bytes = (int64_t)(x.plan.a_f32.size() * 4 + x.plan.a_b16.size() * 2 +
-                                    x.plan.a_x3.size() * 2);
+                                    x.plan.a_x3.size() * 2 + x.plan.geo_cols.size() * 4 +
+                                    x.geo.pts.size() * 4);
     out->workspace_rows = x.plan.ws_rows;
   });
 }

@@ -59,7 +59,10 @@ static int family_of(const LaunchDesc& l) {
 struct Tables {
   KernelFn k[2][3][kNumCfg * kNumFamily];
   dev::BatchedFn b[2][3][kNumCfg * 2];   // [cfg * 2]: batched, [cfg * 2 + 1]: tree pass
+  KernelFn geo[2][3 * kNumCfg];          // [kernel kind * kNumCfg + cfg]: L2L from points
   Tables() {
+    dev::kernels_geo_vec(geo[1]);
+    dev::kernels_geo_any(geo[0]);
     dev::kernels_f32_vec(k[1][PREC_F32], b[1][PREC_F32]);
     dev::kernels_f32_any(k[0][PREC_F32], b[0][PREC_F32]);
     dev::kernels_bf16_vec(k[1][PREC_BF16], b[1][PREC_BF16]);
@@ -73,7 +76,8 @@ static const Tables& tables() {
   return t;
 }
 
-static KernelFn kernel_for(const LaunchDesc& l, int cfg, bool vec) {
+static KernelFn kernel_for(const Compression& c, const LaunchDesc& l, int cfg, bool vec) {
+  if (l.kind == 7) return tables().geo[vec ? 1 : 0][c.geo.kind * kNumCfg + cfg];
   return tables().k[vec ? 1 : 0][l.prec][cfg * kNumFamily + family_of(l)];
 }
 
@@ -84,6 +88,8 @@ struct DeviceState {
   uint16_t* a_b16 = nullptr;
   uint16_t* a_x3 = nullptr;
   i64 x3_plane = 0;
+  float* geo_cols = nullptr;        // geometric mode: column entries per L2L task
+  float* geo_pts = nullptr;         // and the point entries of every index
   TaskDesc* tasks = nullptr;
   i32* rows = nullptr;
   float* ws = nullptr;
@@ -135,6 +141,8 @@ void device_state_free(DeviceState* d) {
   (void)hipFree(d->a_f32);
   (void)hipFree(d->a_b16);
   (void)hipFree(d->a_x3);
+  (void)hipFree(d->geo_cols);
+  (void)hipFree(d->geo_pts);
   (void)hipFree(d->tasks);
   (void)hipFree(d->rows);
   (void)hipFree(d->ws);
@@ -172,6 +180,10 @@ void device_prepare(Compression& c, i64 r_max) {
       }
       upload(&d->tasks, pl.tasks, d->op_bytes);
       upload(&d->rows, pl.rows, d->op_bytes);
+      if (c.geo.kind >= 0) {
+        upload(&d->geo_cols, pl.geo_cols, d->op_bytes);
+        upload(&d->geo_pts, c.geo.pts, d->op_bytes);
+      }
     } catch (...) {
       device_state_free(d);
       throw;
@@ -435,6 +447,15 @@ static bool make_args(Compression& c, int li, int cfg, const EvalArgs& e, dev::K
   a.items = it.first;
   a.A = l.prec == PREC_F32 ? (const void*)d->a_f32 : l.prec == PREC_BF16 ? (const void*)d->a_b16 : (const void*)d->a_x3;
   a.plane = d->x3_plane;
+  a.gpts = nullptr;
+  a.gh2inv = a.gshift = 0.f;
+  a.gacc = l.accumulate;
+  if (l.kind == 7) {
+    a.A = d->geo_cols;
+    a.gpts = d->geo_pts;
+    a.gh2inv = c.geo.h2inv;
+    a.gshift = c.geo.shift;
+  }
   a.rows = d->rows;
   a.W = e.W;
   a.ldw = e.ldw;
@@ -624,7 +645,8 @@ static void launch_seg(Compression& c, const Seg& sg, int cfg, const EvalArgs& e
     if (lo.kind == 6) lo.kind = 1;
     lo.accumulate = 0;
   }
-  hipLaunchKernelGGL(kernel_for(lo, cfg, a.vec != 0), dim3(grid), dim3(kCfgs[cfg].nt), 0, e.stream, a);
+  a.gacc = lo.accumulate;
+  hipLaunchKernelGGL(kernel_for(c, lo, cfg, a.vec != 0), dim3(grid), dim3(kCfgs[cfg].nt), 0, e.stream, a);
   HIP_OK(hipGetLastError());
 }
 
@@ -746,6 +768,7 @@ i64 device_footprint(const Compression& c, i64 r_max) {
   const HostPlan& pl = c.plan;
   i64 b = (i64)(pl.a_f32.size() * 4 + pl.a_b16.size() * 2 + pl.a_x3.size() * 2 +
                 pl.tasks.size() * sizeof(TaskDesc) + pl.rows.size() * 4);
+  if (c.geo.kind >= 0) b += (i64)(pl.geo_cols.size() + c.geo.pts.size()) * 4;
   b += std::max<i64>(1, pl.ws_rows) * ws_cols_for(r_max) * 4;
   // work-item lists: one entry per 32 rows x 32 columns of every task, plus XCD padding
   i64 entries = 0;
@@ -894,6 +917,7 @@ void batch_prepare(int k, Compression* const* c, const i64* r) {
   HIP_OK(hipGetDevice(&cur));
   for (int i = 0; i < k; ++i) {
     if (r[i] < 1) fail(GOFMM_EINVAL, "every instance of a batch needs r >= 1");
+    if (c[i]->geo.kind >= 0) fail(GOFMM_EINVAL, "compressions with device-computed near blocks are evaluated one at a time");
     if (!c[i]->dev || ws_cols_for(r[i]) > c[i]->dev->ws_cols) device_prepare(*c[i], r[i]);
     if (c[i]->dev->device != cur) fail(GOFMM_EINVAL, "current device differs from a compression's device");
   }

@@ -83,7 +83,8 @@ struct LaunchDesc {
   int prec;          // Prec of A for every task in the range
   int accumulate;    // 1: out += A B ; 0: out = A B
   i32 t_begin, t_end;
-  int kind;          // 0 n2s-leaf, 1 n2s-level, 2 s2s, 3 leaf-out, 4 s2n-leaf, 5 l2l, 6 s2n-level
+  int kind;          // 0 n2s-leaf, 1 n2s-level, 2 s2s, 3 leaf-out, 4 s2n-leaf, 5 l2l, 6 s2n-level,
+                     // 7 l2l with the near blocks computed on the device from the points
   int level;
   std::string name;
   double flops = 0;   // per right-hand side: sum of 2 m k over the tasks
@@ -98,6 +99,10 @@ struct HostPlan {
   std::vector<uint16_t> a_b16;
   std::vector<uint16_t> a_x3;        // split BF16: hi plane, then lo plane at x3_plane
   i64 x3_plane = 0;
+  // kind-7 launches: per task, lda column entries of kGeoStride floats (the
+  // column's point, zero-padded to 8 coordinates, then its index as int bits),
+  // at the task's a_off; padding columns have index -1
+  std::vector<float> geo_cols;
   i64 ws_rows = 0;        // 2 * sum of ranks: skeleton weights then potentials
   double flops_phase[4] = {0, 0, 0, 0};     // per right-hand side
   i64 bytes_phase[4] = {0, 0, 0, 0};        // operator bytes read per evaluate
@@ -121,6 +126,20 @@ struct BatchRing {
   int last = -1;
   ~BatchRing();
 };
+
+// Near blocks computed on the device (geometric mode): a radial kernel over
+// points of at most kGeoDim coordinates.
+constexpr int kGeoDim = 8;
+constexpr int kGeoStride = 12;   // floats per point entry: 8 coordinates, index bits, 3 zeros
+struct GeoKernel {
+  int kind = -1;                 // -1: near blocks are stored; else 0 Gaussian, 1 IMQ, 2 Laplacian-like
+  int dim = 0;
+  float h2inv = 0.f, shift = 0.f;
+  std::vector<float> pts;        // n x kGeoStride, original order
+};
+// Kernel, points and parameters of a gofmm_kernel_create state (false if the
+// pointer does not hold one).
+bool kernel_state_geo(const void* state, GeoKernel& out);
 
 // ------------------------------------------------------------------ compression
 struct Compression {
@@ -146,6 +165,8 @@ struct Compression {
   // skeletons
   std::vector<std::vector<i64>> skel, samp;
   std::vector<std::vector<double>> proj;  // s x ncols row-major
+  // near blocks on the device (geometric mode), set by gofmm_use_device_kernel
+  GeoKernel geo;
   // device operator
   HostPlan plan;
   DeviceState* dev = nullptr;

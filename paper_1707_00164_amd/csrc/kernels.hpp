@@ -61,7 +61,23 @@ struct KArgs {
   long long ldws;
   int r;
   int vec;              // rows of W, U, WS are 16-byte aligned and r % 4 == 0
+  // near blocks computed from points (l2l_geo_tiles): point entries of
+  // kGeoStride floats per index (original order), kernel scale, diagonal
+  // shift, and whether the launch accumulates into U
+  const float* gpts;
+  float gh2inv, gshift;
+  int gacc;
 };
+
+// Radial kernel of the geometric mode on a squared distance (GEO = 1 + kind):
+// Gaussian exp(-d2 h2inv / 2), inverse multiquadric 1 / sqrt(1 + d2 h2inv),
+// Laplacian-like 1 / (sqrt(d2) + 0.05).
+template <int GEO>
+__device__ __forceinline__ float geo_kernel(float d2, float h2inv) {
+  if constexpr (GEO == 1) return expf(-0.5f * d2 * h2inv);
+  else if constexpr (GEO == 2) return 1.0f / sqrtf(1.0f + d2 * h2inv);
+  else return 1.0f / (sqrtf(d2) + 0.05f);
+}
 
 // Pointers into device memory as global-address-space pointers, so loads and
 // stores use the global (not generic flat) instructions even when the pointer
@@ -140,9 +156,13 @@ static __device__ __attribute__((aligned(16))) float g_zero16[4];
 // (they bypass the per-XCD L2 caches, which the XCDs do not keep coherent
 // with each other), so a tile can consume rows that a tile on another XCD
 // produced in the same launch without cache write-backs or invalidations.
-template <int PREC, int BM, int BN, int WM, int WN, bool VEC, bool COH = false>
+// GEO > 0: A is not loaded but computed, A(i, k) = kernel(|x_i - x_k|^2) plus
+// the shift where the two indices are equal, from the row's point (held in
+// registers) and the column's point entry (staged through LDS, sg, one slab
+// of 32 columns ahead like B); FP32 only.
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC, bool COH = false, int GEO = 0>
 __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, int m0, int n0, bool accumulate,
-                                          Smem<PREC, BM, BN>& sm) {
+                                          Smem<PREC, BM, BN>& sm, f32x4* sg = nullptr) {
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 32, TN = WTN / 32;
   constexpr int NT = WM * WN * 64;                   // threads per block (4 or 8 waves)
   static_assert((WM * WN == 4 || WM * WN == 8) && TM >= 1 && TN >= 1, "tile shape");
@@ -195,6 +215,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   constexpr int DEP = (!F32 && WM * WN == 4 && BM == 256 && BN == 128) ? 2 : 1;
   u32x4 ra[DEP * NS][NPL][TM];
   auto aload = [&](int slot, int g) {
+    if constexpr (GEO != 0) return;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const bool ok = rb0 + i < nrb && g < kch;
@@ -336,13 +357,54 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       for (int p = 0; p < NPL; ++p) bfr[slot][p][j] = *reinterpret_cast<const u32x4*>(&sm.sB[buf][p][w]);
     }
   };
+  // geometric mode: the lane's row points (rows of its row blocks), and the
+  // column entries of one slab per LDS buffer (32 entries of 3 chunks)
+  constexpr int GCH = KSLAB * 3;
+  [[maybe_unused]] f32x4 xr[GEO ? TM : 1][2];
+  [[maybe_unused]] unsigned int ridx[GEO ? TM : 1];
+  [[maybe_unused]] f32x4 gq = {0.f, 0.f, 0.f, 0.f};
+  [[maybe_unused]] f32x4 gav[2][GEO ? TM : 1];
+  auto gload = [&](int slab) {
+    if constexpr (GEO != 0) {
+      const auto Gc = gmem(reinterpret_cast<const f32x4*>(a.A));
+      if (tid < GCH) gq = Gc[td.a_off / 4 + (long long)min(slab, td.lda / KSLAB - 1) * GCH + tid];
+    }
+  };
+  auto gstore = [&](int buf) {
+    if constexpr (GEO != 0) {
+      if (tid < GCH) sg[buf * GCH + tid] = gq;
+    }
+  };
+  // A values of step s: columns 16 h + 4 s + q of the slab in buffer buf
+  auto gcomp = [&](int slot, int buf, int s) {
+    if constexpr (GEO != 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int col = 16 * lh + 4 * s + q;
+        const f32x4 c0 = sg[buf * GCH + 3 * col], c1 = sg[buf * GCH + 3 * col + 1];
+        const unsigned int cidx = __builtin_bit_cast(u32x4, sg[buf * GCH + 3 * col + 2])[0];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const f32x4 d0 = xr[i][0] - c0, d1 = xr[i][1] - c1;
+          const float d2 = ((d0[0] * d0[0] + d0[1] * d0[1]) + (d0[2] * d0[2] + d0[3] * d0[3])) +
+                           ((d1[0] * d1[0] + d1[1] * d1[1]) + (d1[2] * d1[2] + d1[3] * d1[3]));
+          float v = geo_kernel<GEO>(d2, a.gh2inv);
+          if (ridx[i] == cidx) v += a.gshift;
+          gav[slot][i][q] = v;
+        }
+      }
+    }
+  };
   auto mfma_step = [&](int s, int bs) {
     if constexpr (F32) {
       // (whole vectors are reinterpreted before indexing: a bit cast of a
       // single vector element reads element 0 with this compiler)
       f32x4 av[TM], bv[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) av[i] = __builtin_bit_cast(f32x4, ra[s][0][i]);
+      for (int i = 0; i < TM; ++i) {
+        if constexpr (GEO != 0) av[i] = gav[bs][i];
+        else av[i] = __builtin_bit_cast(f32x4, ra[s][0][i]);
+      }
 #pragma unroll
       for (int j = 0; j < TN; ++j) bv[j] = __builtin_bit_cast(f32x4, bfr[bs][0][j]);
 #pragma unroll
@@ -383,6 +445,24 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   // registers, and an idle wave there would only leave its SIMD idle.)
   constexpr bool IDLE = WM * WN == 8;
   const bool act = !IDLE || __builtin_amdgcn_readfirstlane((rb0 < nrb && n0 + wc * WTN < a.r) ? 1 : 0) != 0;
+  if constexpr (GEO != 0) {
+    static_assert(F32 && DEP == 1, "geometric mode is FP32");
+    const auto Pp = gmem(reinterpret_cast<const f32x4*>(a.gpts));
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int row = m0 + wr * WTM + i * 32 + li;
+      if (row < td.m) {
+        const long long code = codes[td.lda + row];      // a row of U: an original index
+        xr[i][0] = Pp[code * 3];
+        xr[i][1] = Pp[code * 3 + 1];
+        ridx[i] = __builtin_bit_cast(u32x4, Pp[code * 3 + 2])[0];
+      } else {
+        xr[i][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+        xr[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+        ridx[i] = 0xffffffffu;
+      }
+    }
+  }
   if (ns > 0) {
     cload(0);
     bload(0 < td.kws, 0);
@@ -398,6 +478,9 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
     bstore(0, 0, 4, 0);
     bload(DEP * KSLAB < td.kws, 0);
     cload((DEP + 1) * KSLAB);
+    gload(0);
+    gstore(0);
+    gload(1);
   }
   __syncthreads();
   auto iter = [&](int kt, auto setc, auto actc) {
@@ -405,22 +488,32 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
     constexpr int NXT = DEP == 2 ? 1 - SET : 0;      // register set of slabs kt + 1 and kt + 1 + DEP
     constexpr bool ACT = decltype(actc)::value;
     const int buf = kt & 1;
-    if constexpr (ACT) bread(0, buf, 0);
+    if constexpr (ACT) {
+      bread(0, buf, 0);
+      gcomp(0, buf, 0);
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if constexpr (ACT) {
-        if (s + 1 < NS) bread((s + 1) & 1, buf, s + 1);
+        if (s + 1 < NS) {
+          bread((s + 1) & 1, buf, s + 1);
+          gcomp((s + 1) & 1, buf, s + 1);
+        }
         mfma_step(SET * NS + s, s & 1);
         aload(SET * NS + s, (kt + DEP) * NS + s);
       }
       // slab kt + 1 into the other buffer (no wave reads it before the
       // barrier below), then the B rows of slab kt + 1 + DEP and the codes of
       // the slab after; past the last slab these move data that nobody reads
-      if (s == 0) bstore(buf ^ 1, 0, 2, NXT);
+      if (s == 0) {
+        bstore(buf ^ 1, 0, 2, NXT);
+        gstore(buf ^ 1);
+      }
       if (s == 1) {
         bstore(buf ^ 1, 2, 4, NXT);
         bload((kt + 1 + DEP) * KSLAB < td.kws, NXT);
         cload((kt + 2 + DEP) * KSLAB);
+        gload(kt + 2);
       }
       // one matrix-core instruction at a time, with the step's LDS traffic,
       // global loads and vector work placed in its shadow
@@ -500,6 +593,19 @@ template <int PREC, int BM, int BN, int WM, int WN, bool ACC, bool VEC>
 __global__ __launch_bounds__(WM * WN * 64) void leaf_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, ACC, VEC>(a); }
 
 typedef void (*KernelFn)(KArgs);
+
+// L2L with the near blocks computed from the points (GEO = 1 + kernel kind);
+// whether it accumulates into U comes with the arguments.
+template <int BM, int BN, int WM, int WN, bool VEC, int GEO>
+__global__ __launch_bounds__(WM * WN * 64) void l2l_geo_tiles(KArgs a) {
+  __shared__ Smem<PREC_F32, BM, BN> sm;
+  __shared__ f32x4 sg[2 * 32 * 3];
+  const int2 it = a.items[blockIdx.x];
+  if (it.x < 0) return;
+  const TaskDesc td = a.tasks[it.x];
+  tile_body<PREC_F32, BM, BN, WM, WN, VEC, false, GEO>(a, td, (it.y >> 16) * BM, (it.y & 0xffff) * BN,
+                                                      a.gacc != 0, sm, sg);
+}
 
 // ------------------------------------------------------------ persistent launches
 // Several steps (of one or of many compressions) in one persistent launch.
@@ -678,6 +784,29 @@ void fill_table(KernelFn* table, BatchedFn* persistent) {
   fill_family<PREC, 256, 128, 8, 1, VEC>(table + 10 * kNumFamily, persistent + 20);
 }
 
+// geo[kind * kNumCfg + cfg], the same tile shapes as fill_table
+template <bool VEC, int GEO>
+void fill_geo_kind(KernelFn* t) {
+  t[0] = l2l_geo_tiles<128, 128, 2, 2, VEC, GEO>;
+  t[1] = l2l_geo_tiles<128, 64, 2, 2, VEC, GEO>;
+  t[2] = l2l_geo_tiles<64, 128, 2, 2, VEC, GEO>;
+  t[3] = l2l_geo_tiles<64, 64, 2, 2, VEC, GEO>;
+  t[4] = l2l_geo_tiles<128, 32, 4, 1, VEC, GEO>;
+  t[5] = l2l_geo_tiles<32, 128, 1, 4, VEC, GEO>;
+  t[6] = l2l_geo_tiles<256, 128, 4, 1, VEC, GEO>;
+  t[7] = l2l_geo_tiles<128, 256, 2, 2, VEC, GEO>;
+  t[8] = l2l_geo_tiles<256, 128, 4, 2, VEC, GEO>;
+  t[9] = l2l_geo_tiles<128, 256, 2, 4, VEC, GEO>;
+  t[10] = l2l_geo_tiles<256, 128, 8, 1, VEC, GEO>;
+}
+template <bool VEC>
+void fill_geo(KernelFn* t) {
+  static_assert(kNumCfg == 11, "geometric tile table");
+  fill_geo_kind<VEC, 1>(t);
+  fill_geo_kind<VEC, 2>(t + kNumCfg);
+  fill_geo_kind<VEC, 3>(t + 2 * kNumCfg);
+}
+
 // One translation unit per (precision, row alignment).
 void kernels_f32_vec(KernelFn* table, BatchedFn* batched);
 void kernels_f32_any(KernelFn* table, BatchedFn* batched);
@@ -685,6 +814,8 @@ void kernels_bf16_vec(KernelFn* table, BatchedFn* batched);
 void kernels_bf16_any(KernelFn* table, BatchedFn* batched);
 void kernels_x3_vec(KernelFn* table, BatchedFn* batched);
 void kernels_x3_any(KernelFn* table, BatchedFn* batched);
+void kernels_geo_vec(KernelFn* table);
+void kernels_geo_any(KernelFn* table);
 
 }  // namespace dev
 }  // namespace gofmm

@@ -24,6 +24,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <cstring>
+
 #include "internal.hpp"
 
 namespace gofmm {
@@ -53,7 +55,8 @@ int elem_bytes(int prec) { return prec == PREC_BF16 ? 2 : 4; }
 
 // One part of a task's A: either a P-based block or a kernel block.
 struct Part {
-  int type;        // 0: P_h (s x ncols); 1: P_h^T restricted (see cols); 2: K(rows, cols)
+  int type;        // 0: P_h (s x ncols); 1: P_h^T restricted (see cols); 2: K(rows, cols);
+                   // 3: K(rows, cols) computed on the device (nothing stored)
   i64 node;        // for types 0/1
   i64 c0, c1;      // column range of P_h for type 1 (rows of P^T)
   std::vector<i64> krows, kcols;  // for type 2 (original indices)
@@ -62,6 +65,7 @@ struct Part {
 
 struct Draft {
   int prec;
+  bool geo = false;        // A computed on the device from points (kind-7 launch)
   i64 m;
   std::vector<Part> parts;
   std::vector<i32> brow;   // B row codes (k of them)
@@ -180,7 +184,39 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
       leaf_rows(a, d.brow);
     }
   };
-  if (D >= 1 && pst != pnear) {
+  if (c.geo.kind >= 0) {
+    // geometric mode: S2N at the leaf from the stored P^T, then L2L with the
+    // near blocks computed on the device (FP32) from the points
+    if (D >= 1) {
+      begin_launch(pst, 0, 4, D, "s2n_leaf");
+      for (i64 b = 0; b < L; ++b) {
+        const i64 h = fl + b;
+        Draft d;
+        d.prec = pst;
+        d.m = c.node_size[h];
+        d.parts.push_back({1, h, 0, c.node_size[h], {}, {}, c.rank(h)});
+        for (i64 j = 0; j < c.rank(h); ++j) d.brow.push_back(urow(h, j));
+        leaf_rows(h, d.orow);
+        drafts.push_back(std::move(d));
+      }
+      end_launch();
+    }
+    begin_launch(PREC_F32, D >= 1 ? 1 : 0, 7, D, "l2l");
+    for (i64 b = 0; b < L; ++b) {
+      const i64 h = fl + b;
+      Draft d;
+      d.prec = PREC_F32;
+      d.geo = true;
+      d.m = c.node_size[h];
+      for (i64 a : c.near[h - fl]) {
+        d.parts.push_back({3, 0, 0, 0, {}, {}, c.node_size[a]});
+        leaf_rows(a, d.brow);
+      }
+      leaf_rows(h, d.orow);
+      drafts.push_back(std::move(d));
+    }
+    end_launch();
+  } else if (D >= 1 && pst != pnear) {
     begin_launch(pst, 0, 4, D, "s2n_leaf");
     for (i64 b = 0; b < L; ++b) {
       const i64 h = fl + b;
@@ -227,6 +263,7 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
   const i64 T = (i64)drafts.size();
   pl.tasks.resize(T);
   i64 off[3] = {0, 0, 0};
+  i64 goff = 0;
   i64 roff = 0;
   for (i64 t = 0; t < T; ++t) {
     Draft& d = drafts[t];
@@ -243,9 +280,14 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
       if (code >= 0) break;
       ++td.kws;
     }
-    td.a_off = off[d.prec];
     td.idx_off = roff;
-    off[d.prec] += rows_stored(d.m) * lda;
+    if (d.geo) {
+      td.a_off = goff;
+      goff += lda * kGeoStride;
+    } else {
+      td.a_off = off[d.prec];
+      off[d.prec] += rows_stored(d.m) * lda;
+    }
     roff += lda + d.m;
   }
   pl.rows.assign(roff, ROW_ZERO);
@@ -259,21 +301,40 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
   pl.a_b16.assign(off[PREC_BF16], 0);
   pl.x3_plane = off[PREC_BF16X3];
   pl.a_x3.assign(2 * off[PREC_BF16X3], 0);
+  pl.geo_cols.assign(goff, 0.0f);
+  for (i64 t = 0; t < T; ++t) {
+    const Draft& d = drafts[t];
+    if (!d.geo) continue;
+    const TaskDesc& td = pl.tasks[t];
+    for (i64 j = 0; j < td.lda; ++j) {
+      float* e = &pl.geo_cols[td.a_off + j * kGeoStride];
+      if (j < td.k) {
+        const i32 code = d.brow[j];
+        if (code < 0 || code >= c.n) fail(GOFMM_EINVAL, "internal: near column code");
+        std::copy(c.geo.pts.begin() + (size_t)code * kGeoStride,
+                  c.geo.pts.begin() + (size_t)(code + 1) * kGeoStride, e);
+      } else {
+        const int32_t none = -1;
+        std::memcpy(&e[kGeoDim], &none, sizeof(none));
+      }
+    }
+  }
 
   // flop and byte accounting per right-hand side (Table 2)
   for (size_t li = 0; li < pl.launches.size(); ++li) {
     LaunchDesc& l = pl.launches[li];
     for (i32 t = l.t_begin; t < l.t_end; ++t) {
       const Draft& d = drafts[t];
+      if (d.geo) l.bytes += pl.tasks[t].lda * kGeoStride * (i64)sizeof(float);
       for (const Part& p : d.parts) {
         l.flops += 2.0 * (double)d.m * (double)p.width;
-        l.bytes += d.m * p.width * elem_bytes(d.prec);
+        if (!d.geo) l.bytes += d.m * p.width * elem_bytes(d.prec);
         int ph;
         if (p.type == 0) ph = PH_N2S;
         else if (p.type == 1) ph = PH_S2N;
         else ph = (l.kind == 2) ? PH_S2S : PH_L2L;
         pl.flops_phase[ph] += 2.0 * (double)d.m * (double)p.width;
-        pl.bytes_phase[ph] += d.m * p.width * elem_bytes(d.prec);
+        if (!d.geo) pl.bytes_phase[ph] += d.m * p.width * elem_bytes(d.prec);
       }
     }
   }
@@ -286,6 +347,7 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
   for (i64 t = 0; t < T; ++t) {
     try {
       const Draft& d = drafts[t];
+      if (d.geo) continue;                      // computed on the device
       const TaskDesc& td = pl.tasks[t];
       const i64 m = d.m, k = td.k;
       std::vector<double> A((size_t)m * std::max<i64>(k, 1), 0.0);

@@ -6,13 +6,17 @@
 // coordinate as (x_i - x_j)^2, so K(i, j) == K(j, i) bitwise.
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <new>
 
 #include "internal.hpp"
 
 namespace {
 
+constexpr unsigned kStateMagic = 0x6b65726eu;
+
 struct KernelState {
+  unsigned magic = kStateMagic;
   int kind;
   gofmm::i64 n;
   int dim;
@@ -39,6 +43,27 @@ inline double entry(const KernelState& s, gofmm::i64 i, gofmm::i64 j) {
 }
 
 }  // namespace
+
+namespace gofmm {
+
+bool kernel_state_geo(const void* state, GeoKernel& out) {
+  const KernelState* s = static_cast<const KernelState*>(state);
+  if (!s || s->magic != kStateMagic || s->dim > kGeoDim) return false;
+  out.kind = s->kind;
+  out.dim = s->dim;
+  out.h2inv = (float)s->h2inv;
+  out.shift = (float)s->shift;
+  out.pts.assign((size_t)s->n * kGeoStride, 0.0f);
+  for (i64 i = 0; i < s->n; ++i) {
+    float* e = &out.pts[(size_t)i * kGeoStride];
+    for (int c = 0; c < s->dim; ++c) e[c] = (float)s->x[(size_t)i * s->dim + c];
+    const int32_t idx = (int32_t)i;
+    std::memcpy(&e[kGeoDim], &idx, sizeof(idx));
+  }
+  return true;
+}
+
+}  // namespace gofmm
 
 extern "C" int gofmm_kernel_create(int32_t kind, int64_t n, int32_t dim, const double* points,
                                    double h, double shift, void** state) {
@@ -80,4 +105,8 @@ extern "C" int gofmm_kernel_sample(void* state, int64_t nI, const int64_t* I, in
   return 0;
 }
 
-extern "C" void gofmm_kernel_free(void* state) { delete static_cast<KernelState*>(state); }
+extern "C" void gofmm_kernel_free(void* state) {
+  KernelState* s = static_cast<KernelState*>(state);
+  if (s) s->magic = 0;
+  delete s;
+}

@@ -364,6 +364,7 @@ extern "C" int gofmm_server_add(gofmm_server* h, gofmm_compression* c, int64_t r
   return sguard([&] {
     if (!h || !c || !model) fail(GOFMM_EINVAL, "NULL argument");
     if (r_max < 1) fail(GOFMM_EINVAL, "r_max must be >= 1");
+    if (c->c.geo.kind >= 0) fail(GOFMM_EINVAL, "compressions with device-computed near blocks are not served");
     Server& s = h->s;
     std::lock_guard<std::mutex> g(s.mu);
     for (auto& kv : s.models)

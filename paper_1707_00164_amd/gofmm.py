@@ -65,6 +65,7 @@ SIGNATURES = [
     ("gofmm_default_params", None, [C.POINTER(Params)]),
     ("gofmm_compress", C.c_int, [C.c_int64, SAMPLER, C.c_void_p, C.POINTER(Params), C.POINTER(C.c_void_p)]),
     ("gofmm_import", C.c_int, [C.c_char_p, SAMPLER, C.c_void_p, C.POINTER(Params), C.POINTER(C.c_void_p)]),
+    ("gofmm_use_device_kernel", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
     ("gofmm_export", C.c_int, [C.c_void_p, C.c_char_p]),
     ("gofmm_prepare", C.c_int, [C.c_void_p, C.c_int64]),
     ("gofmm_evaluate", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
@@ -223,6 +224,13 @@ class Compression:
 
     def export(self, path: str):
         _check(lib().gofmm_export(self.h, path.encode()))
+
+    def use_device_kernel(self, sampler: "KernelSampler", threads: int = 0):
+        """Compute the near blocks on the device from the sampler's points
+        (the sampler must describe this compression's matrix)."""
+        if not isinstance(sampler, KernelSampler):
+            raise TypeError("needs the library's KernelSampler")
+        _check(lib().gofmm_use_device_kernel(self.h, sampler.state, int(threads)))
 
     def prepare(self, r_max: int):
         _check(lib().gofmm_prepare(self.h, r_max))

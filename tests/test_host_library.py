@@ -243,3 +243,50 @@ def test_footprint_grows_with_r(small):
     st = comp.stats()
     assert f1 >= st.operator_bytes
     assert f2 - f1 >= st.workspace_rows * 1020 * 4
+
+
+def _geo_comp(g, n=1500, dim=3, kind="gaussian", h=0.3, shift=1e-3):
+    rng = np.random.default_rng(31)
+    pts = rng.random((n, dim))
+    S = g.KernelSampler(pts, kind, h, shift)
+    comp = g.Compression.compress(S, leaf_size=100, max_rank=48, tol=1e-6, kappa=16, budget=0.1, seed=3)
+    return pts, S, comp
+
+
+def test_device_kernel_plan_drops_near_blocks(g):
+    """Computing the near blocks on the device leaves the method's work
+    unchanged (same flops per phase) and removes the stored near blocks from
+    the operator: the leaf output splits into S2N at the leaves (stored P^T)
+    and an L2L launch that reads only point entries."""
+    pts, S, comp = _geo_comp(g)
+    st0 = comp.stats()
+    names0 = [l[0] for l in comp.launches()]
+    comp.use_device_kernel(S)
+    st1 = comp.stats()
+    names1 = [l[0] for l in comp.launches()]
+    assert names0[-1] == "leaf" and names1[-2:] == ["s2n_leaf", "l2l"]
+    assert names1[:-2] == names0[:-1]
+    assert list(st1.flops_phase) == list(st0.flops_phase)
+    assert st1.operator_bytes_phase[3] == 0                       # no stored L2L operator
+    # a stored near block holds 4 m bytes per column, its replacement one
+    # 48-byte point entry per column (m ~ 94 here: about an eighth)
+    near_bytes = st0.operator_bytes_phase[3]
+    assert near_bytes > 0 and st1.operator_bytes < st0.operator_bytes - 0.7 * near_bytes
+    l2l = comp.launches()[-1]
+    assert l2l[1] == pytest.approx(st1.flops_phase[3])            # all L2L flops in the one launch
+
+
+def test_device_kernel_rejects_bad_arguments(g):
+    pts, S, comp = _geo_comp(g, n=800)
+    other = g.KernelSampler(pts[:700], "gaussian", 0.3, 1e-3)    # another n
+    with pytest.raises(g.GofmmError):
+        comp.use_device_kernel(other)
+    nine = g.KernelSampler(np.random.default_rng(1).random((800, 9)), "gaussian", 0.3, 1e-3)
+    with pytest.raises(g.GofmmError):
+        comp.use_device_kernel(nine)                               # more than 8 coordinates
+    with pytest.raises(TypeError):
+        comp.use_device_kernel(g.PySampler(lambda I, J: np.zeros((len(I), len(J))), 800))
+    assert g.lib().gofmm_use_device_kernel(None, S.state, 0) == -1                 # GOFMM_EINVAL
+    assert g.lib().gofmm_use_device_kernel(comp.h, None, 0) == -1                 # GOFMM_EINVAL
+    comp.use_device_kernel(S)                                      # still usable after the errors
+    assert [l[0] for l in comp.launches()][-1] == "l2l"

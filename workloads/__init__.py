@@ -90,10 +90,17 @@ def batched_instances(count: int = 48) -> List[Workload]:
     return out
 
 
+def _serving_budget(n: int, m: int) -> float:
+    """3%, or enough for 4 other near leaves per leaf where that is more."""
+    return max(0.03, 4.5 * m / n)
+
+
 def serving_instances(count: int = 16, n_lo: int = 16384, n_hi: int = 262144) -> List[Workload]:
     """Resident compressions for the serving loop: N log-spaced in [n_lo, n_hi],
     kernels cycling through the three families above; leaf size and maximum
-    rank are the family's, at least 256 (512 from N = 131072 up)."""
+    rank are the family's, at least 256 (512 from N = 131072 up); near budget
+    3%, raised for small trees so that a leaf may take at least 4 other near
+    leaves (cap = floor(budget N / m))."""
     ns = np.unique(np.round(np.geomspace(n_lo, n_hi, count)).astype(np.int64))
     fams = [small_gaussian(), clustered_gaussian(), large_imq()]
     out = []
@@ -102,15 +109,15 @@ def serving_instances(count: int = 16, n_lo: int = 16384, n_hi: int = 262144) ->
         m = max(f.leaf_size, 256 if n < 131072 else 512)
         out.append(dataclasses.replace(
             f, name=f"serve{k:02d}_{f.kernel}_n{n}", n=int(n), leaf_size=m, max_rank=m,
-            budget=0.03, seed=_cfg_seed(5, k + 1)))
+            budget=_serving_budget(int(n), m), seed=_cfg_seed(5, k + 1)))
     return out
 
 
 def serving_admissions(count: int = 4, n_lo: int = 16384, n_hi: int = 65536) -> List[Workload]:
     """Fresh compressions admitted while the serving loop runs: N log-spaced
     in [n_lo, n_hi], kernels cycling through the three families (leaf size
-    and maximum rank the family's, at least 256), seeds disjoint from the
-    resident ones."""
+    and maximum rank the family's, at least 256; budget as for the resident
+    set), seeds disjoint from the resident ones."""
     ns = np.round(np.geomspace(n_lo, n_hi, count)).astype(np.int64)
     fams = [small_gaussian(), clustered_gaussian(), large_imq()]
     out = []
@@ -119,7 +126,7 @@ def serving_admissions(count: int = 4, n_lo: int = 16384, n_hi: int = 65536) -> 
         m = max(f.leaf_size, 256)
         out.append(dataclasses.replace(
             f, name=f"admit{k:02d}_{f.kernel}_n{n}", n=int(n), leaf_size=m, max_rank=m,
-            budget=0.03, seed=_cfg_seed(5, 100 + k)))
+            budget=_serving_budget(int(n), m), seed=_cfg_seed(5, 100 + k)))
     return out
 
 
