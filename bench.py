@@ -558,9 +558,10 @@ def main():
     ap.add_argument("--precisions", nargs="+", default=["fp32", "bf16", "bf16x3"])
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark measures one GPU only; every box here has one "
-                                   "GPU and the evaluator has no multi-GPU path (see DESIGN.md "
-                                   "for how it would shard)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark measures one GPU only: the evaluator has no "
+                                   "multi-GPU path (it would shard by subtrees, with one exchange of "
+                                   "skeleton weights and near-field W rows after the upward pass)",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

@@ -268,7 +268,7 @@ def sample_rows(members: np.ndarray, knn: np.ndarray, n: int, ncols: int, rng) -
     return take.astype(np.int64)
 
 
-# ---------------------------------------------------------------- driver
+# ---------------------------------------------------------------- top level
 def compress(K, n: int, *, leaf_size: int, max_rank: int, tol: float, kappa: int,
              budget: float, distance_kind: int = GRAM_L2, seed: int = 0,
              knn: Optional[np.ndarray] = None, refine: bool = True) -> Compression:

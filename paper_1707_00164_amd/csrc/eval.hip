@@ -51,6 +51,7 @@ static int family_of(const LaunchDesc& l) {
   if (l.kind == 0 || l.kind == 1) return 0;
   if (l.kind == 2) return 1;
   if (l.kind == 6) return 2;
+  if (l.kind == 4 && !l.accumulate) return 5;
   return l.accumulate ? 4 : 3;
 }
 

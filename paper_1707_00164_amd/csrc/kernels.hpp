@@ -594,6 +594,8 @@ template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
 __global__ __launch_bounds__(WM * WN * 64) void s2n_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, true, VEC>(a); }
 template <int PREC, int BM, int BN, int WM, int WN, bool ACC, bool VEC>
 __global__ __launch_bounds__(WM * WN * 64) void leaf_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, ACC, VEC>(a); }
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
+__global__ __launch_bounds__(WM * WN * 64) void s2n_leaf_tiles(KArgs a) { gemm_tiles<PREC, BM, BN, WM, WN, false, VEC>(a); }
 
 typedef void (*KernelFn)(KArgs);
 
@@ -752,7 +754,7 @@ __global__ __launch_bounds__(WM * WN * 64) void pass_tiles(BArgs b) { persistent
 
 typedef void (*BatchedFn)(BArgs);
 constexpr int kNumCfg = 11;
-constexpr int kNumFamily = 5;   // n2s, s2s, s2n (accumulate), leaf, leaf accumulating
+constexpr int kNumFamily = 6;   // n2s, s2s, s2n (accumulate), leaf, leaf accumulating, s2n at the leaves
 struct Cfg { int bm, bn, nt; };   // tile rows, tile columns, threads per block
 constexpr Cfg kCfgs[kNumCfg] = {{128, 128, 256}, {128, 64, 256}, {64, 128, 256}, {64, 64, 256},
                                 {128, 32, 256},  {32, 128, 256}, {256, 128, 256}, {128, 256, 256},
@@ -767,6 +769,7 @@ void fill_family(KernelFn* row, BatchedFn* brow) {
   row[2] = s2n_tiles<PREC, BM, BN, WM, WN, VEC>;
   row[3] = leaf_tiles<PREC, BM, BN, WM, WN, false, VEC>;
   row[4] = leaf_tiles<PREC, BM, BN, WM, WN, true, VEC>;
+  row[5] = s2n_leaf_tiles<PREC, BM, BN, WM, WN, VEC>;
 }
 
 // table[cfg * kNumFamily + family], persistent[cfg * 2 + (0 batched, 1 pass)]

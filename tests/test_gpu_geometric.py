@@ -166,3 +166,24 @@ def test_geometric_not_batched_or_served(torch):
     with pytest.raises(g.GofmmError):
         srv.add(comp, 8)
     srv.close()
+
+
+def test_geometric_one_column_and_strided_rows(torch):
+    """r = 1 and W, U with row strides larger than r (columns past r of U
+    untouched)."""
+    rng = np.random.default_rng(13)
+    n = 2100
+    pts = rng.random((n, 5))
+    S, comp = _compress(pts, "gaussian", 0.4, 1e-3)
+    comp.use_device_kernel(S)
+    K = kernels.KernelMatrix(pts, "gaussian", 0.4, 1e-3)
+    for r, ld in ((1, 1), (6, 11)):
+        log(f"case geometric r={r} ld={ld}")
+        W64, Wd = cuda_rhs(n, r, 40 + r, ld)
+        big = torch.full((n, ld + 3), 7.0, device="cuda")
+        Ud = big[:, :r]
+        comp.evaluate(Wd, Ud)
+        torch.cuda.synchronize()
+        ref = evaluate.tree_walk(export_read(comp), K, Wd.cpu().numpy().astype(np.float64))
+        _check(Ud.cpu().numpy(), ref, what=f"r={r} ld={ld}")
+        assert torch.all(big[:, r:] == 7.0)
