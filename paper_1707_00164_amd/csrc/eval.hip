@@ -687,10 +687,10 @@ void device_evaluate(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
 }
 
 // Time every configuration of every segment for this r and keep the fastest.
-// A shape replaces the fastest one timed so far only if it is faster by 2%:
-// timings within the noise keep the earlier (simpler) shape, so the choice is
-// stable from run to run.
-constexpr float kTuneMargin = 0.98f;
+// A shape replaces the fastest one timed so far only if it is faster by 4%:
+// timings within the noise (and within what a profiler's own overhead shifts)
+// keep the earlier (simpler) shape, so the choice is stable from run to run.
+constexpr float kTuneMargin = 0.96f;
 
 void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i64 ldu, void* stream,
                      int reps) {
