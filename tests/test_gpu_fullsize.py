@@ -160,3 +160,29 @@ def test_batched_instances_subset():
         e = rel_err(Us[i].cpu().numpy()[rows], ref)
         log(f"  instance {i} (N={w.n}) vs oracle {e:.2e}")
         assert e <= 1e-5
+
+
+def test_large_imq_r2048_fp32_and_split_bf16(large):
+    """The largest configuration the benchmark times: r = 2048 right-hand
+    sides on the N=262144 compression, FP32 and split BF16, 64 sampled rows
+    against one FP64 oracle walk."""
+    import torch
+    g, w, S, comp, c, K, rows, path = large
+    r = 2048
+    log(f"case {w.name} r={r} fp32 and split bf16, 64 sampled rows")
+    W = torch.from_numpy(workloads.rhs(w.n, r, w.seed + 1).astype(np.float32)).cuda()
+    W64 = W.cpu().numpy().astype(np.float64)
+    ref = evaluate.tree_walk(c, K, W64, rows)
+    exact = dense.kw(K, W64, rows)
+    for name, prec, tol in (("fp32", g.FP32, 1e-5), ("bf16x3", g.BF16X3, 3e-5)):
+        cc = g.Compression.load(path, S, storage=prec, near_storage=prec)
+        U = cc.autotune(W)
+        torch.cuda.synchronize()
+        got = U.cpu().numpy()[rows]
+        e = rel_err(got, ref)
+        eps = rel_err(got, exact)
+        log(f"  {name}: vs oracle {e:.2e}, eps2 vs exact {eps:.2e}")
+        assert e <= tol and eps <= 1e-4
+        del U
+        cc.free()
+        torch.cuda.empty_cache()
