@@ -522,6 +522,63 @@ def form_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def form_sweep(args):
+    """Accuracy against time over the method's knobs (the analogue of the
+    paper's HSS-versus-FMM and distance studies, Sec. 4): the N=65536
+    clustered Gaussian at r=512 compressed with near budget 0 (HSS), 1%, 3%
+    and 10%, maximum rank 64, 128 and 256, and the Gram-l2 and Gram-angle
+    distances; each compression evaluated autotuned in FP32 and split BF16,
+    error against the exact K W on 64 sampled rows."""
+    import numpy as np
+    import tempfile
+    import torch
+    import workloads
+    import paper_1707_00164_amd as g
+    w = workloads.clustered_gaussian()
+    pts = workloads.points(w)
+    S = g.KernelSampler(pts, w.kernel, w.h, w.shift)
+    W = torch.from_numpy(workloads.rhs(w.n, w.r, w.seed).astype(np.float32)).cuda()
+    U = torch.empty_like(W)
+    rows = workloads.sample_rows(w.n, 64, w.seed)
+    exact = exact_rows(S, W, rows)
+    res = []
+    for dist_name, dist in (("gram_l2", g.GRAM_L2), ("angle", g.ANGLE)):
+        for budget in (0.0, 0.01, 0.03, 0.10):
+            for s_max in (64, 128, 256):
+                t0 = time.perf_counter()
+                comp = g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=s_max, tol=w.tol,
+                                              kappa=w.kappa, budget=budget, distance=dist, seed=w.seed)
+                t_comp = time.perf_counter() - t0
+                st = comp.stats()
+                fd, path = tempfile.mkstemp(suffix=".gofmm")
+                os.close(fd)
+                comp.export(path)
+                item = {"distance": dist_name, "budget": budget, "max_rank": s_max,
+                        "compress_s": round(t_comp, 2), "mean_rank": round(st.rank_sum / (st.n_nodes - 1), 1),
+                        "near_pairs": st.near_pairs, "far_pairs": st.far_pairs,
+                        "flops_per_step": st.flops_per_rhs * w.r}
+                for name, prec in (("fp32", g.FP32), ("bf16x3", g.BF16X3)):
+                    c = comp if name == "fp32" else g.Compression.load(path, S, storage=prec, near_storage=prec)
+                    c.autotune(W, U)
+                    sec = _timed(lambda: c.evaluate(W, U), args.steps, args.warmup, torch)
+                    got = U.cpu().numpy()[rows].astype(np.float64)
+                    item[name] = {"ms_per_step": round(sec * 1e3, 4),
+                                  "value": round(2.0 * w.n * w.n * w.r / sec / 1e9, 1),
+                                  "eps2_vs_exact_KW": float(f"{np.linalg.norm(got - exact) / np.linalg.norm(exact):.3e}"),
+                                  "operator_gb": round(c.stats().operator_bytes / 1e9, 3)}
+                    c.free()
+                os.unlink(path)
+                torch.cuda.empty_cache()
+                res.append(item)
+                log(f"{dist_name} budget {budget:.2f} s {s_max}: rank {item['mean_rank']}, fp32 "
+                    f"{item['fp32']['ms_per_step']} ms eps {item['fp32']['eps2_vs_exact_KW']:.2e}, bf16x3 "
+                    f"{item['bf16x3']['ms_per_step']} ms eps {item['bf16x3']['eps2_vs_exact_KW']:.2e}")
+    out = {"metric": METRIC, "form": "sweep", "unit": "ms", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": w.name, "n": w.n, "r": w.r, "leaf_size": w.leaf_size, "tol": w.tol,
+                      "kappa": w.kappa}, "results": res}
+    print(json.dumps(out), flush=True)
+
+
 def form_copy(args):
     """A device-to-device copy of exactly 1 GiB (counter calibration: the
     traffic counters of this copy should read 1 GiB fetched, 1 GiB written)."""
@@ -544,9 +601,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-geometric", action="store_true", help="skip the near-blocks-from-points form")
     ap.add_argument("--rows", type=int, default=256, help="rows compared with the oracle and with exact K W")
-    ap.add_argument("--form", default="flat", choices=["flat", "batched", "serving", "large", "copy"],
+    ap.add_argument("--form", default="flat", choices=["flat", "batched", "serving", "large", "sweep", "copy"],
                     help="flat: the N=65536 workload (default); batched: 48 compressions in one launch; "
-                         "serving: request loop with p50/p99; large: N=262144 in three precisions")
+                         "serving: request loop with p50/p99; large: N=262144 in three precisions; "
+                         "sweep: accuracy and time over budget, rank and distance")
     ap.add_argument("--instances", type=int, default=48, help="batched form: compressions")
     ap.add_argument("--models", type=int, default=16, help="serving form: resident compressions")
     ap.add_argument("--admissions", type=int, default=4, help="serving form: compressions admitted per Poisson run")
@@ -573,7 +631,7 @@ def main():
     g.lib()
     if args.form != "flat":
         {"batched": form_batched, "serving": form_serving, "large": form_large,
-         "copy": form_copy}[args.form](args)
+         "sweep": form_sweep, "copy": form_copy}[args.form](args)
         return
     w = workloads.clustered_gaussian()
     pts = workloads.points(w)
