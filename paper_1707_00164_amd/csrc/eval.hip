@@ -247,7 +247,11 @@ static std::pair<int2*, int> items_for(Compression& c, int li, int cfg, int ntn)
   int2* dp = nullptr;
   if (!v.empty()) {
     HIP_OK(hipMalloc((void**)&dp, v.size() * sizeof(int2)));
-    HIP_OK(hipMemcpy(dp, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice));
+    const hipError_t e = hipMemcpy(dp, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(dp);
+      fail(GOFMM_EHIP, std::string("hipMemcpy of work items: ") + hipGetErrorString(e));
+    }
   }
   d->items[key] = {dp, (int)v.size()};
   return d->items[key];
@@ -687,6 +691,24 @@ void device_evaluate(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
 }
 
 // Time every configuration of every segment for this r and keep the fastest.
+// Two timing events, destroyed on every exit path.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    HIP_OK(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      fail(GOFMM_EHIP, "hipEventCreate failed");
+    }
+  }
+  ~EventPair() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  EventPair(const EventPair&) = delete;
+  EventPair& operator=(const EventPair&) = delete;
+};
+
 // A shape replaces the fastest one timed so far only if it is faster by 4%:
 // timings within the noise (and within what a profiler's own overhead shifts)
 // keep the earlier (simpler) shape, so the choice is stable from run to run.
@@ -696,11 +718,15 @@ void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
                      int reps) {
   device_evaluate(c, r, W, ldw, U, ldu, stream);          // prepares and warms up
   hipStream_t st = (hipStream_t)stream;
-  hipEvent_t e0, e1;
-  HIP_OK(hipEventCreate(&e0));
-  HIP_OK(hipEventCreate(&e1));
+  EventPair ev;
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   const EvalArgs e{r, W, ldw, U, ldu, st};
-  const bool prof = c.dev->profiling;
+  // per-launch profiling is off while timing, and restored on every exit path
+  struct ProfOff {
+    DeviceState* d;
+    bool was;
+    ~ProfOff() { d->profiling = was; }
+  } prof_off{c.dev, c.dev->profiling};
   c.dev->profiling = false;
   for (const Seg& sg : segments(c.plan)) {
     float best = 1e30f;
@@ -720,9 +746,6 @@ void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
     }
     c.dev->tuned[{sg.pass ? -(sg.j0 + 1) : sg.j0, r}] = bc;
   }
-  c.dev->profiling = prof;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   // the timing runs overwrote intermediate rows: recompute a clean result
   device_evaluate(c, r, W, ldw, U, ldu, stream);
 }
@@ -964,9 +987,8 @@ void device_autotune_batched(int k, Compression* const* c, const i64* r, const f
     std::lock_guard<std::mutex> g(api_mutex());
     batch_prepare(k, c, r);
     hipStream_t st = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
+    EventPair ev;
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     float best = 1e30f;
     int bc = batch_cfg_model(k, c, r);
     for (int q = 0; q < kNumCfg; ++q) {
@@ -981,8 +1003,6 @@ void device_autotune_batched(int k, Compression* const* c, const i64* r, const f
         std::fprintf(stderr, "tune batched k=%d cfg %dx%dx%d: %.4f ms\n", k, kCfgs[q].bm, kCfgs[q].bn, kCfgs[q].nt, ms / reps);
       if (ms < kTuneMargin * best) { best = ms; bc = q; }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     batch_tuned()[batch_key(k, c, r)] = bc;
   }
   device_evaluate_batched(k, c, r, W, ldw, U, ldu, stream);
