@@ -111,15 +111,24 @@ void gofmm_default_params(gofmm_params* p);
  * with a symmetric refinement, nested IDs in FP64 (eqs. 7-8, Alg. 5), and the
  * cached blocks Kba / SKba packed for the device in the requested precision.
  * Host only: no GPU is touched until gofmm_prepare or the first evaluate.
+ * params may be NULL (defaults).  On success *out is a new compression the
+ * caller releases with gofmm_free.  Errors: GOFMM_EINVAL (n < 1, NULL
+ * sampler or out, parameters out of range), GOFMM_ECALLBACK (the sampler
+ * failed), GOFMM_ENOTSPD (K_ii <= 0 or a non-finite entry), GOFMM_ENOMEM,
+ * GOFMM_ELIMIT (n or the operator beyond 32-bit row codes); *out is NULL.
  */
 int gofmm_compress(int64_t n, gofmm_sampler sampler, void* user,
                    const gofmm_params* params, gofmm_compression** out);
 
 /*
- * Load the structure (tree, permutation, lists, skeletons, P) written by
- * gofmm_export or by an external tool in the same format, and sample the
- * cached blocks with `sampler`.  params supplies storage precisions and
- * threads only; the method parameters come from the file.
+ * Load the structure that Alg. Compress produces (Sec. 2.2: tree and
+ * permutation, Near and Far lists, skeletons and the interpolation matrices
+ * P of eqs. 7-8) as written by gofmm_export or by an external tool in the
+ * same format, check it (a partition, coverage of every leaf pair, nested
+ * skeletons), and sample the cached blocks with `sampler`.  params supplies
+ * storage precisions and threads only; the method parameters come from the
+ * file.  Ownership and errors as for gofmm_compress, plus GOFMM_EIO for a
+ * file that cannot be read or does not hold a valid structure.
  */
 int gofmm_import(const char* path, gofmm_sampler sampler, void* user,
                  const gofmm_params* params, gofmm_compression** out);
@@ -145,7 +154,10 @@ int gofmm_import(const char* path, gofmm_sampler sampler, void* user,
  */
 int gofmm_use_device_kernel(gofmm_compression* c, void* kernel_state, int32_t threads);
 
-/* Write the structure of a compression (no kernel blocks) to `path`. */
+/* Write the structure of a compression (tree, permutation, lists, skeletons,
+ * P; no kernel blocks) to `path`, the format gofmm_import and the test
+ * oracle read.  GOFMM_EINVAL for NULL arguments, GOFMM_EIO if the file
+ * cannot be written. */
 int gofmm_export(const gofmm_compression* c, const char* path);
 
 /*
@@ -167,6 +179,9 @@ int gofmm_prepare(gofmm_compression* c, int64_t r_max);
  * the downward pass then each run as one launch whose tiles wait for the
  * tiles they read, through counters that only grow).  r == 0 is a no-op;
  * r > r_max of a previous prepare grows the workspace synchronously.
+ * Errors: GOFMM_EINVAL (NULL c, W or U, r < 0, ldw or ldu < r, W and U
+ * overlapping, a compression prepared on another device), GOFMM_ENOMEM (the
+ * workspace), GOFMM_EHIP (a launch or copy failed).
  */
 int gofmm_evaluate(gofmm_compression* c, int64_t r,
                    const float* W, int64_t ldw, float* U, int64_t ldu,
@@ -182,10 +197,18 @@ int gofmm_autotune(gofmm_compression* c, int64_t r,
                    void* hip_stream);
 
 /*
- * k independent products U_i = K~_i W_i in one persistent launch: a single
- * grid walks the union of all instances' tiles, with per-instance level
- * counters ordering the upward and downward passes.  Same argument rules as
- * gofmm_evaluate, per instance.  The k compressions must be distinct.
+ * k independent products U_i = K~_i W_i (Alg. Evaluate for each, Sec. 2.2)
+ * in one persistent launch: a single grid walks the union of all instances'
+ * tiles in step order, and a tile waits only for the tasks whose rows it
+ * reads (a node's N2S for its children's, S2S for the upward pass, a node's
+ * S2N for its parent's and its own S2S, the leaf output for its S2N), through
+ * counters of finished tiles.  Same argument rules as gofmm_evaluate, per
+ * instance; arrays c, r, W, ldw, U, ldu hold k entries each (k == 0 is a
+ * no-op).  The k compressions must be distinct and share one storage
+ * precision.  Errors: GOFMM_EINVAL (k < 0, NULL arrays or entries, a repeated
+ * compression, outputs of two instances that overlap, mixed precisions, r < 1,
+ * a compression in device-kernel mode),
+ * GOFMM_EHIP.
  */
 int gofmm_evaluate_batched(int32_t k, gofmm_compression* const* c, const int64_t* r,
                            const float* const* W, const int64_t* ldw,
@@ -224,9 +247,11 @@ int gofmm_evaluate_status(gofmm_compression* c, int32_t* error);
 
 /*
  * Launches of one evaluate, in order.  For launch i: its name (e.g. "n2s_leaf",
- * "s2s_l3", "leaf"), the Table 2 flops it performs per right-hand side, and
- * the operator bytes it reads.  name receives at most name_len bytes
- * including the terminator.
+ * "n2s_l3", "s2s", "s2n_l4", "leaf"), the Table 2 flops it performs per
+ * right-hand side (2 m k summed over its tasks, internal N2S/S2N counted as
+ * 2 s_a (s_l + s_r)), and the operator bytes it reads.  name receives at
+ * most name_len bytes including the terminator.  GOFMM_EINVAL for NULL
+ * arguments or i outside [0, count).
  */
 int gofmm_launch_count(const gofmm_compression* c, int32_t* count);
 int gofmm_launch_info(const gofmm_compression* c, int32_t i, char* name, int32_t name_len,
@@ -244,10 +269,13 @@ int gofmm_launch_info(const gofmm_compression* c, int32_t i, char* name, int32_t
 int gofmm_profile(gofmm_compression* c, int32_t enable);
 int gofmm_profile_read(gofmm_compression* c, int32_t n, float* total_ms, int32_t* calls);
 
-/* Device bytes a prepared compression holds for r_max right-hand sides. */
+/* Device bytes a compression holds once prepared for r_max right-hand sides
+ * (operator, tables, work-item lists, workspace); host-side, no GPU call.
+ * GOFMM_EINVAL for NULL arguments or r_max < 1. */
 int gofmm_footprint(const gofmm_compression* c, int64_t r_max, int64_t* bytes);
 
-/* Fill `out` with the summary of c. */
+/* Fill `out` with the summary of c (flops per phase as Table 2 counts them,
+ * see gofmm_launch_info).  GOFMM_EINVAL for NULL arguments. */
 int gofmm_stats(const gofmm_compression* c, gofmm_stats_t* out);
 
 /* Release a compression (host and device).  NULL is ignored. */
