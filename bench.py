@@ -96,8 +96,20 @@ def roofline(comp, dom, dom_ms, share, r, form, near_form=None):
                 traffic = t.get("bytes_per_launch")
         except Exception:
             traffic = None
+    # matrix-core busy cycles from the counters (SQ_VALU_MFMA_BUSY_CYCLES over
+    # 1024 SIMDs x the launch's cycles), taken on the same kernel sources
+    mfma = None
+    mfile = os.path.join(ROOT, "profiles", "mfma_counters.json")
+    if os.path.exists(mfile):
+        try:
+            for e in json.load(open(mfile)):
+                if e.get("launch") == name and e.get("form") == form and e.get("fingerprint") == _fingerprint():
+                    mfma = {"mfma_busy_frac": round(e["mfma_busy_frac"], 4), "clock_ghz": round(e["clock_ghz"], 3),
+                            "counted_tflops": round(e["counted_tflops"], 1)}
+        except Exception:
+            mfma = None
     out = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-           "frac": round(achieved / peak, 4), "traffic": traffic,
+           "frac": round(achieved / peak, 4), "traffic": traffic, "mfma_counters": mfma,
            "kernel": name, "avg_launch_ms": round(avg_s * 1e3, 4),
            "flops_per_launch": fl * r, "operator_bytes_per_launch": byts,
            "launch_time_share": share}
