@@ -714,6 +714,20 @@ struct EventPair {
 // keep the earlier (simpler) shape, so the choice is stable from run to run.
 constexpr float kTuneMargin = 0.96f;
 
+void device_profile_read(Compression& c, int n, float* total_ms, int* calls);
+
+// Tile shape per launch, timed in context: for each launch in turn and each
+// shape, `reps` whole evaluates run with that launch on that shape and HIP
+// events around that launch alone, so every shape is timed with the caches,
+// the accumulation and the clock the launch meets inside an evaluate (a
+// launch repeated on its own keeps its operands cached and, for short
+// launches, measures something else).  Launches not yet tuned use the cost
+// model's shape.  When that many evaluates would take more than
+// kInContextBudgetMs (large problems, whose launches are long enough to time
+// alone), and for the persistent tree passes (opt-in), each shape is timed by
+// repeating the launch on its own.
+constexpr double kInContextBudgetMs = 5000.0;
+
 void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i64 ldu, void* stream,
                      int reps) {
   device_evaluate(c, r, W, ldw, U, ldu, stream);          // prepares and warms up
@@ -721,32 +735,60 @@ void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
   EventPair ev;
   hipEvent_t e0 = ev.a, e1 = ev.b;
   const EvalArgs e{r, W, ldw, U, ldu, st};
-  // per-launch profiling is off while timing, and restored on every exit path
-  struct ProfOff {
+  float t_eval = 0.f;
+  HIP_OK(hipEventRecord(e0, st));
+  device_evaluate(c, r, W, ldw, U, ldu, stream);
+  HIP_OK(hipEventRecord(e1, st));
+  HIP_OK(hipEventSynchronize(e1));
+  HIP_OK(hipEventElapsedTime(&t_eval, e0, e1));
+  const bool in_context =
+      (double)t_eval * (double)c.plan.launches.size() * kNumCfg * (reps + 1) <= kInContextBudgetMs;
+  // the caller's profiling state is restored on every exit path
+  struct ProfRestore {
     DeviceState* d;
     bool was;
-    ~ProfOff() { d->profiling = was; }
-  } prof_off{c.dev, c.dev->profiling};
+    int only;
+    ~ProfRestore() {
+      d->profiling = was;
+      d->prof_only = only;
+    }
+  } restore{c.dev, c.dev->profiling, c.dev->prof_only};
   c.dev->profiling = false;
+  const int nl = (int)c.plan.launches.size();
+  std::vector<float> ms(nl);
+  std::vector<int> calls(nl);
+  device_profile_read(c, nl, ms.data(), calls.data());   // drop earlier records
   for (const Seg& sg : segments(c.plan)) {
     float best = 1e30f;
     int bc = choose_cfg(c, sg.j0, r);
     for (int q = 0; q < kNumCfg; ++q) {
-      launch_seg(c, sg, q, e, true);
-      HIP_OK(hipEventRecord(e0, st));
-      for (int t = 0; t < reps; ++t) launch_seg(c, sg, q, e, true);
-      HIP_OK(hipEventRecord(e1, st));
-      HIP_OK(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < kTuneMargin * best) { best = ms; bc = q; }
+      float t = 0.f;
+      if (sg.pass || !in_context) {
+        launch_seg(c, sg, q, e, true);
+        HIP_OK(hipEventRecord(e0, st));
+        for (int k = 0; k < reps; ++k) launch_seg(c, sg, q, e, true);
+        HIP_OK(hipEventRecord(e1, st));
+        HIP_OK(hipEventSynchronize(e1));
+        HIP_OK(hipEventElapsedTime(&t, e0, e1));
+        t /= reps;
+      } else {
+        c.dev->tuned[{sg.j0, r}] = q;
+        device_evaluate(c, r, W, ldw, U, ldu, stream);  // item lists for this shape, warm
+        c.dev->profiling = true;
+        c.dev->prof_only = sg.j0;
+        for (int k = 0; k < reps; ++k) device_evaluate(c, r, W, ldw, U, ldu, stream);
+        c.dev->profiling = false;
+        device_profile_read(c, nl, ms.data(), calls.data());
+        t = ms[sg.j0] / std::max(1, calls[sg.j0]);
+      }
+      if (t < kTuneMargin * best) { best = t; bc = q; }
       if (std::getenv("GOFMM_TUNE_LOG"))
         std::fprintf(stderr, "tune %s%s r=%lld cfg %dx%dx%d: %.4f ms\n", c.plan.launches[sg.j0].name.c_str(),
-                     sg.pass ? " (pass)" : "", (long long)r, kCfgs[q].bm, kCfgs[q].bn, kCfgs[q].nt, ms / reps);
+                     sg.pass ? " (pass)" : "", (long long)r, kCfgs[q].bm, kCfgs[q].bn, kCfgs[q].nt, t);
     }
     c.dev->tuned[{sg.pass ? -(sg.j0 + 1) : sg.j0, r}] = bc;
   }
-  // the timing runs overwrote intermediate rows: recompute a clean result
+  // timing runs on their own overwrote intermediate rows: a clean result
   device_evaluate(c, r, W, ldw, U, ldu, stream);
 }
 
