@@ -190,7 +190,10 @@ int gofmm_evaluate(gofmm_compression* c, int64_t r,
 /*
  * Same product as gofmm_evaluate, after timing every tile configuration of
  * every launch for this r and keeping the fastest (later evaluates with the
- * same r reuse the choice).  Synchronizes the stream.
+ * same r reuse the choice).  Each configuration is timed inside whole
+ * evaluates (events around the tuned launch only) when all of them fit a few
+ * seconds, else by repeating the launch on its own.  Synchronizes the
+ * stream.  Errors as for gofmm_evaluate.
  */
 int gofmm_autotune(gofmm_compression* c, int64_t r,
                    const float* W, int64_t ldw, float* U, int64_t ldu,
