@@ -187,3 +187,27 @@ def test_geometric_one_column_and_strided_rows(torch):
         ref = evaluate.tree_walk(export_read(comp), K, Wd.cpu().numpy().astype(np.float64))
         _check(Ud.cpu().numpy(), ref, what=f"r={r} ld={ld}")
         assert torch.all(big[:, r:] == 7.0)
+
+
+def test_geometric_with_persistent_tree_passes(torch, monkeypatch):
+    """The opt-in persistent upward and downward passes in front of the
+    device-computed near field give the same bits as separate launches."""
+    import paper_1707_00164_amd as g
+    rng = np.random.default_rng(17)
+    n = 5000
+    pts = rng.random((n, 4))
+    S, comp = _compress(pts, "gaussian", 0.4, 1e-3, leaf_size=96)
+    comp.use_device_kernel(S)
+    W64, Wd = cuda_rhs(n, 40, 6)
+    monkeypatch.setenv("GOFMM_PASSES", "0")
+    ref = comp.evaluate(Wd)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    monkeypatch.setenv("GOFMM_PASSES", "1")
+    log(f"case geometric with persistent passes: launches {[l[0] for l in comp.launches()]}")
+    U = torch.empty_like(Wd)
+    for rep in range(3):
+        comp.evaluate(Wd, U)
+        torch.cuda.synchronize()
+        assert np.array_equal(U.cpu().numpy(), ref), rep
+    assert comp.status() == 0
