@@ -56,12 +56,15 @@ enum { GOFMM_FP32 = 0,      /* FP32 storage, FP32 matrix-core products */
 typedef struct gofmm_compression gofmm_compression;   /* opaque */
 
 /*
- * Entry sampler: the method's only input (Sec. 1, problem statement).
- * Fill out[i * ld + j] = K(I[i], J[j]) in FP64 (row-major, ld >= nJ) for
- * original indices I[0..nI), J[0..nJ).  K must be symmetric (K(i,j) == K(j,i)
- * bitwise) and positive definite.  Called only inside gofmm_compress and
- * gofmm_import, possibly from several threads at once (params.threads).
- * Return 0; any other value aborts the call with GOFMM_ECALLBACK.
+ * Entry sampler: the method's only input (Sec. 1, problem statement: a
+ * routine returning the block K(I, J) for any index sets I and J).
+ * Fill out[i + j * ld] = K(I[i], J[j]) in FP64 for original indices
+ * I[0..nI), J[0..nJ): an nI x nJ column-major block with leading dimension
+ * ld >= nI (cells outside the block must not be written).  K must be
+ * symmetric (K(i,j) == K(j,i) bitwise) and positive definite.  Called only
+ * inside gofmm_compress, gofmm_import and gofmm_use_device_kernel, possibly
+ * from several threads at once (params.threads).  Return 0; any other value
+ * aborts the call with GOFMM_ECALLBACK.
  */
 typedef int (*gofmm_sampler)(void* user, int64_t nI, const int64_t* I,
                              int64_t nJ, const int64_t* J, double* out, int64_t ld);
@@ -145,12 +148,13 @@ int gofmm_import(const char* path, gofmm_sampler sampler, void* user,
  * are dropped from the operator, and every evaluate computes them in FP32,
  * entry by entry from the points (kernel of the squared distance, summed
  * coordinate by coordinate, plus the shift where the two indices are equal),
- * inside the L2L launch, whatever near_storage says.  Any device copy of the
- * compression is released first.  Compressions in this mode cannot be
+ * inside the L2L launch, whatever near_storage says.  On success the device
+ * copy of the previous plan is released (the next prepare or evaluate uploads
+ * the new one).  Compressions in this mode cannot be
  * batched or served (GOFMM_EINVAL there).  Errors: GOFMM_EINVAL for NULL
  * arguments, a pointer that is not such a state, more than 8 coordinates or a
- * different n; sampling errors as for gofmm_compress, after which c holds no
- * operator and can only be freed.
+ * different n; sampling errors as for gofmm_compress, after which c is
+ * unchanged (its previous plan and device copy stay in use).
  */
 int gofmm_use_device_kernel(gofmm_compression* c, void* kernel_state, int32_t threads);
 
@@ -360,6 +364,8 @@ void gofmm_server_destroy(gofmm_server* s);
  */
 int gofmm_kernel_create(int32_t kind, int64_t n, int32_t dim, const double* points,
                         double h, double shift, void** state);
+/* Sampler layout as above (out[i + j * ld], ld >= nI); returns 1 for a NULL
+ * state or arrays or ld < nI, 2 for an index outside [0, n). */
 int gofmm_kernel_sample(void* state, int64_t nI, const int64_t* I,
                         int64_t nJ, const int64_t* J, double* out, int64_t ld);
 void gofmm_kernel_free(void* state);

@@ -122,17 +122,22 @@ extern "C" int gofmm_use_device_kernel(gofmm_compression* c, void* kernel_state,
     if (!kernel_state_geo(kernel_state, g))
       fail(GOFMM_EINVAL, "not a gofmm_kernel_create state, or points with more than 8 coordinates");
     if ((i64)(g.pts.size() / kGeoStride) != c->c.n) fail(GOFMM_EINVAL, "the kernel's point count differs from n");
-    if (c->c.dev) {                   // the plan changes: drop the device copy
-      device_state_free(c->c.dev);
-      c->c.dev = nullptr;
-    }
+    // Build the new plan next to the old one; a failure restores the old plan
+    // and point set, and the device copy of the old plan stays valid.
+    HostPlan old_plan = std::move(c->c.plan);
+    GeoKernel old_geo = std::move(c->c.geo);
     c->c.geo = std::move(g);
     Sampler K{gofmm_kernel_sample, kernel_state};
     try {
       build_plan(c->c, K, threads > 0 ? threads : omp_get_max_threads());
     } catch (...) {
-      c->c.geo = GeoKernel();
+      c->c.plan = std::move(old_plan);
+      c->c.geo = std::move(old_geo);
       throw;
+    }
+    if (c->c.dev) {                   // the plan changed: drop the old device copy
+      device_state_free(c->c.dev);
+      c->c.dev = nullptr;
     }
   });
 }

@@ -60,17 +60,18 @@ void parallel_for(i64 n, int threads, F body) {
   if (failed) fail(code, msg);
 }
 
-// Sample K(I, J) (row-major nI x nJ), splitting rows over threads when large.
+// Sample K(I, J) (column-major nI x nJ, leading dimension nI), splitting rows
+// over threads when large.
 void sample(const Sampler& K, const i64* I, i64 nI, const i64* J, i64 nJ, double* out, int threads) {
   const i64 chunk = std::max<i64>(1, (1 << 16) / std::max<i64>(1, nJ));
   const i64 nchunks = (nI + chunk - 1) / chunk;
   if (nchunks <= 1 || omp_in_parallel() || threads <= 1) {
-    K(nI, I, nJ, J, out);
+    K(nI, I, nJ, J, out, nI);
     return;
   }
   parallel_for(nchunks, threads, [&](i64 c) {
     const i64 a = c * chunk, b = std::min(nI, a + chunk);
-    K(b - a, I + a, nJ, J, out + a * nJ);
+    K(b - a, I + a, nJ, J, out + a, nI);
   });
 }
 
@@ -124,7 +125,7 @@ void metric_split(const Dist& d, const std::vector<i64>& idx, Rng& rng, std::vec
   if (d.kind == GOFMM_GRAM_L2) {
     for (i64 t = 0; t < n; ++t) {
       double s = 0.0;
-      for (i64 j = 0; j < nc; ++j) s += kic[t * nc + j];
+      for (i64 j = 0; j < nc; ++j) s += kic[t + j * n];
       dc[t] = d.diag[idx[t]] - 2.0 * s / nc;        // |phi_i - c|^2 minus |c|^2
     }
   } else {
@@ -135,7 +136,7 @@ void metric_split(const Dist& d, const std::vector<i64>& idx, Rng& rng, std::vec
     cc /= (double)(nc * nc);
     for (i64 t = 0; t < n; ++t) {
       double s = 0.0;
-      for (i64 j = 0; j < nc; ++j) s += kic[t * nc + j];
+      for (i64 j = 0; j < nc; ++j) s += kic[t + j * n];
       s /= nc;
       dc[t] = 1.0 - s * s / (d.diag[idx[t]] * cc);
     }
@@ -282,7 +283,7 @@ void neighbours(Compression& c, const Dist& d, const gofmm_params& p) {
       for (i64 a = 0; a < m; ++a) {
         const i64 i = idx[a];
         cand.resize(m);
-        for (i64 t = 0; t < m; ++t) cand[t] = {d.from(blk[a * m + t], i, idx[t]), idx[t]};
+        for (i64 t = 0; t < m; ++t) cand[t] = {d.from(blk[a + t * m], i, idx[t]), idx[t]};
         merge_list(&c.knn[(size_t)i * kappa], &kd[(size_t)i * kappa], kappa, cand);
       }
     });
@@ -520,8 +521,8 @@ void build_compression(Compression& c, const Sampler& K, const gofmm_params& p) 
         std::sort(extra.begin(), extra.end());
         rows.insert(rows.end(), extra.begin(), extra.end());
       }
-      std::vector<double> A((size_t)rows.size() * ncols);
-      K((i64)rows.size(), rows.data(), ncols, cols.data(), A.data());
+      std::vector<double> A((size_t)rows.size() * ncols);     // column-major
+      K((i64)rows.size(), rows.data(), ncols, cols.data(), A.data(), (i64)rows.size());
       for (double x : A)
         if (!std::isfinite(x)) fail(GOFMM_ENOTSPD, "sampler returned a non-finite entry");
       std::vector<int> piv;

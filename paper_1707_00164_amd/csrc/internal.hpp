@@ -51,10 +51,11 @@ inline int level_of(i64 h) { int l = 0; while (((h + 1) >> (l + 1)) != 0) ++l; r
 struct Sampler {
   gofmm_sampler fn = nullptr;
   void* user = nullptr;
-  // out: nI x nJ row-major with leading dimension ld (default nJ)
+  // The callback's own layout: out[i + j * ld] = K(I[i], J[j]), an nI x nJ
+  // column-major block with leading dimension ld >= nI (default nI).
   void operator()(i64 nI, const i64* I, i64 nJ, const i64* J, double* out, i64 ld = -1) const {
     if (nI == 0 || nJ == 0) return;
-    int rc = fn(user, nI, I, nJ, J, out, ld < 0 ? nJ : ld);
+    int rc = fn(user, nI, I, nJ, J, out, ld < 0 ? nI : ld);
     if (rc != 0) fail(GOFMM_ECALLBACK, "sampler returned " + std::to_string(rc));
   }
 };
@@ -193,8 +194,9 @@ void validate_structure(const Compression& c);
 void write_file(const Compression& c, const char* path);
 void read_file(Compression& c, const char* path);
 
-// FP64 ID of a row-major nrow x ncol block A (overwritten): returns rank s and
-// fills piv (ncol entries, first s are the skeleton columns) and P (s x ncol).
+// FP64 ID of a column-major nrow x ncol block A (leading dimension nrow,
+// overwritten by the factorization): returns rank s and fills piv (ncol
+// entries, first s are the skeleton columns) and P (s x ncol, row-major).
 int interp_decomp(double* A, int nrow, int ncol, double tol, int smax,
                   std::vector<int>& piv, std::vector<double>& P);
 

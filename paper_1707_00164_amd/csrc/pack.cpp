@@ -350,22 +350,24 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
       if (d.geo) continue;                      // computed on the device
       const TaskDesc& td = pl.tasks[t];
       const i64 m = d.m, k = td.k;
+      // A column-major (leading dimension m), the sampler's own layout, so
+      // kernel blocks are sampled in place
       std::vector<double> A((size_t)m * std::max<i64>(k, 1), 0.0);
       i64 col = 0;
       for (const Part& p : d.parts) {
         if (p.type == 0) {
           const i64 nc = c.ncols(p.node);
           const double* P = c.proj[p.node].data();
-          for (i64 i = 0; i < m; ++i)
-            for (i64 j = 0; j < nc; ++j) A[i * k + col + j] = P[i * nc + j];
+          for (i64 j = 0; j < nc; ++j)
+            for (i64 i = 0; i < m; ++i) A[i + (col + j) * m] = P[i * nc + j];
         } else if (p.type == 1) {
           // rows c0..c1 of P_node^T = columns c0..c1 of P_node
           const i64 nc = c.ncols(p.node), s = c.rank(p.node);
           const double* P = c.proj[p.node].data();
-          for (i64 i = 0; i < p.c1 - p.c0; ++i)
-            for (i64 j = 0; j < s; ++j) A[i * k + col + j] = P[j * nc + p.c0 + i];
+          for (i64 j = 0; j < s; ++j)
+            for (i64 i = 0; i < p.c1 - p.c0; ++i) A[i + (col + j) * m] = P[j * nc + p.c0 + i];
         } else {
-          K((i64)p.krows.size(), p.krows.data(), (i64)p.kcols.size(), p.kcols.data(), &A[col], k);
+          K((i64)p.krows.size(), p.krows.data(), (i64)p.kcols.size(), p.kcols.data(), &A[col * m], m);
         }
         col += p.width;
       }
@@ -374,18 +376,18 @@ void build_plan(Compression& c, const Sampler& K, int threads) {
       const i64 lda = td.lda;
       if (d.prec == PREC_F32) {
         float* dst = &pl.a_f32[td.a_off];
-        for (i64 i = 0; i < m; ++i)
-          for (i64 j = 0; j < k; ++j) dst[frag_pos_f32(i, j, lda)] = (float)A[i * k + j];
+        for (i64 j = 0; j < k; ++j)
+          for (i64 i = 0; i < m; ++i) dst[frag_pos_f32(i, j, lda)] = (float)A[i + j * m];
       } else if (d.prec == PREC_BF16) {
         uint16_t* dst = &pl.a_b16[td.a_off];
-        for (i64 i = 0; i < m; ++i)
-          for (i64 j = 0; j < k; ++j) dst[frag_pos_b16(i, j, lda)] = to_bf16(A[i * k + j]);
+        for (i64 j = 0; j < k; ++j)
+          for (i64 i = 0; i < m; ++i) dst[frag_pos_b16(i, j, lda)] = to_bf16(A[i + j * m]);
       } else {
         uint16_t* hi = &pl.a_x3[td.a_off];
         uint16_t* lo = &pl.a_x3[pl.x3_plane + td.a_off];
-        for (i64 i = 0; i < m; ++i)
-          for (i64 j = 0; j < k; ++j) {
-            const double x = A[i * k + j];
+        for (i64 j = 0; j < k; ++j)
+          for (i64 i = 0; i < m; ++i) {
+            const double x = A[i + j * m];
             const uint16_t h = to_bf16(x);
             hi[frag_pos_b16(i, j, lda)] = h;
             lo[frag_pos_b16(i, j, lda)] = to_bf16(x - from_bf16(h));

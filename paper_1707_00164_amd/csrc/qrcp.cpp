@@ -22,9 +22,7 @@ namespace gofmm {
 int interp_decomp(double* A, int nrow, int ncol, double tol, int smax,
                   std::vector<int>& piv, std::vector<double>& P) {
   const size_t ld = (size_t)nrow;
-  std::vector<double> C(ld * ncol);                    // column-major working copy
-  for (int i = 0; i < nrow; ++i)
-    for (int j = 0; j < ncol; ++j) C[(size_t)j * ld + i] = A[(size_t)i * ncol + j];
+  double* C = A;                                       // factored in place, column-major
   piv.resize(ncol);
   for (int j = 0; j < ncol; ++j) piv[j] = j;
   std::vector<double> nrm(ncol), ref(ncol);

@@ -93,14 +93,13 @@ extern "C" int gofmm_kernel_create(int32_t kind, int64_t n, int32_t dim, const d
 extern "C" int gofmm_kernel_sample(void* state, int64_t nI, const int64_t* I, int64_t nJ,
                                    const int64_t* J, double* out, int64_t ld) {
   const KernelState* s = static_cast<const KernelState*>(state);
-  if (!s || (nI && !I) || (nJ && !J) || !out || ld < nJ) return 1;
-  for (int64_t a = 0; a < nI; ++a) {
+  if (!s || (nI && !I) || (nJ && !J) || !out || ld < nI) return 1;
+  for (int64_t a = 0; a < nI; ++a)
     if (I[a] < 0 || I[a] >= s->n) return 2;
-    double* row = out + a * ld;
-    for (int64_t b = 0; b < nJ; ++b) {
-      if (J[b] < 0 || J[b] >= s->n) return 2;
-      row[b] = entry(*s, I[a], J[b]);
-    }
+  for (int64_t b = 0; b < nJ; ++b) {
+    if (J[b] < 0 || J[b] >= s->n) return 2;
+    double* col = out + b * ld;                // column-major: out[a + b * ld]
+    for (int64_t a = 0; a < nI; ++a) col[a] = entry(*s, I[a], J[b]);
   }
   return 0;
 }

@@ -152,14 +152,14 @@ class KernelSampler:
         """K(I, J) in FP64 (original indices), from the library's sampler."""
         I = np.ascontiguousarray(I, dtype=np.int64)
         J = np.ascontiguousarray(J, dtype=np.int64)
-        out = np.empty((len(I), len(J)), dtype=np.float64)
+        out = np.empty((len(I), len(J)), dtype=np.float64, order="F")   # column-major, ld = |I|
         if len(I) and len(J):
             rc = lib().gofmm_kernel_sample(self.state, len(I), I.ctypes.data_as(C.POINTER(C.c_int64)), len(J),
                                            J.ctypes.data_as(C.POINTER(C.c_int64)),
-                                           out.ctypes.data_as(C.POINTER(C.c_double)), len(J))
+                                           out.ctypes.data_as(C.POINTER(C.c_double)), len(I))
             if rc != 0:
                 raise GofmmError(rc, "kernel sampler failed")
-        return out
+        return np.ascontiguousarray(out)
 
     def __del__(self):
         if getattr(self, "state", None) and _lib is not None:
@@ -179,8 +179,13 @@ class PySampler:
                 ii = np.ctypeslib.as_array(I, shape=(nI,)).copy()
                 jj = np.ctypeslib.as_array(J, shape=(nJ,)).copy()
                 blk = np.asarray(fn(ii, jj), dtype=np.float64)
-                dst = np.ctypeslib.as_array(out, shape=(nI, ld))
-                dst[:, :nJ] = blk
+                if blk.shape != (nI, nJ):
+                    return 1
+                # column-major block: out[i + j * ld] = K(I[i], J[j]); only the
+                # cells of the block are written (the last column has nI)
+                dst = np.ctypeslib.as_array(out, shape=((nJ - 1) * ld + nI,))
+                for j in range(nJ):
+                    dst[j * ld:j * ld + nI] = blk[:, j]
                 return 0
             except Exception:
                 return 1

@@ -290,3 +290,104 @@ def test_device_kernel_rejects_bad_arguments(g):
     assert g.lib().gofmm_use_device_kernel(comp.h, None, 0) == -1                 # GOFMM_EINVAL
     comp.use_device_kernel(S)                                      # still usable after the errors
     assert [l[0] for l in comp.launches()][-1] == "l2l"
+
+
+def test_sampler_layout_is_column_major(g):
+    """The sampler contract (a routine returning K(I, J), Sec. 1 problem
+    statement) fills out[i + j * ld], an nI x nJ column-major block with
+    ld >= nI, and leaves every other cell alone: checked on the built-in
+    sampler with nI != nJ and ld > nI, against scalar kernel entries."""
+    import math
+    rng = np.random.default_rng(4)
+    n, h, shift = 60, 0.4, 1e-2
+    pts = rng.random((n, 3))
+    S = g.KernelSampler(pts, "imq", h, shift)
+    I = np.array([3, 17, 5], dtype=np.int64)
+    J = np.array([9, 3, 41, 0, 59], dtype=np.int64)
+    ld = 7
+    buf = np.full(ld * len(J), -7.0)
+    rc = g.lib().gofmm_kernel_sample(S.state, len(I), I.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(J),
+                                     J.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ld)
+    assert rc == 0
+    for j in range(len(J)):
+        for i in range(ld):
+            v = buf[i + j * ld]
+            if i >= len(I):
+                assert v == -7.0                      # outside the block: untouched
+                continue
+            d2 = math.fsum((pts[I[i], c] - pts[J[j], c]) ** 2 for c in range(3))
+            want = 1.0 / math.sqrt(1.0 + d2 / (h * h)) + (shift if I[i] == J[j] else 0.0)
+            assert abs(v - want) <= 1e-15 * want
+    # ld < nI is refused
+    assert g.lib().gofmm_kernel_sample(S.state, len(I), I.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(J),
+                                       J.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2) == 1
+
+
+def test_library_reads_column_major_sampler_blocks(g):
+    """A C-ABI callback written to the contract (column-major, ld >= nI) gives
+    the same compression as the built-in sampler on the same matrix: every
+    block the library requests (rows x columns of different sizes, for the
+    tree, the neighbours, the IDs and the cached blocks) is read in that
+    layout.  The callback also checks that ld >= nI on every call."""
+    rng = np.random.default_rng(8)
+    n = 900
+    pts = rng.random((n, 3))
+    A = kernels.KernelMatrix(pts, "gaussian", 0.35, 1e-3)(np.arange(n), np.arange(n))
+    seen = {"calls": 0, "bad_ld": 0, "rect": 0}
+
+    def cb(user, nI, I, nJ, J, out, ld):
+        seen["calls"] += 1
+        if ld < nI:
+            seen["bad_ld"] += 1
+            return 1
+        if nI != nJ:
+            seen["rect"] += 1
+        ii = np.ctypeslib.as_array(I, shape=(nI,))
+        jj = np.ctypeslib.as_array(J, shape=(nJ,))
+        dst = np.ctypeslib.as_array(out, shape=((nJ - 1) * ld + nI,))
+        blk = A[np.ix_(ii, jj)]
+        for j in range(nJ):
+            dst[j * ld:j * ld + nI] = blk[:, j]
+        return 0
+
+    fn = g.gofmm.SAMPLER(cb)
+
+    class Raw:
+        pass
+
+    raw = Raw()
+    raw.n, raw.fn, raw.state = n, fn, None
+    kw = dict(leaf_size=64, max_rank=40, tol=1e-6, kappa=8, budget=0.05, seed=9, threads=1)
+    c1 = export_read(g.Compression.compress(raw, **kw))
+    c2 = export_read(g.Compression.compress(g.PySampler(lambda I, J: A[np.ix_(I, J)], n), **kw))
+    assert seen["calls"] > 0 and seen["bad_ld"] == 0 and seen["rect"] > 0
+    assert np.array_equal(c1.perm, c2.perm)
+    for h in range(1, c1.nn):
+        assert np.array_equal(c1.skel[h], c2.skel[h])
+        assert np.array_equal(c1.proj[h], c2.proj[h])
+    W = workloads.rhs(n, 2, 3)
+    assert dense.eps2(evaluate.tree_walk(c1, kernels.DenseMatrix(A), W), A @ W) < 1e-2
+
+
+def test_device_kernel_failure_leaves_compression_unchanged(g):
+    """A failed switch to device-computed near blocks (here the state's points
+    give non-finite entries, so sampling the new plan fails) leaves the
+    compression's plan, flop counts and structure as they were."""
+    pts, S, comp = _geo_comp(g, n=900)
+    names0 = [l[0] for l in comp.launches()]
+    st0 = comp.stats()
+    bad_pts = pts.copy()
+    bad_pts[5, 1] = np.nan
+    bad = g.KernelSampler(bad_pts, "gaussian", 0.3, 1e-3)
+    with pytest.raises(g.GofmmError) as e:
+        comp.use_device_kernel(bad)
+    assert e.value.code == -3                                        # GOFMM_ENOTSPD
+    assert [l[0] for l in comp.launches()] == names0
+    st1 = comp.stats()
+    assert st1.operator_bytes == st0.operator_bytes
+    assert list(st1.flops_phase) == list(st0.flops_phase)
+    assert list(st1.operator_bytes_phase) == list(st0.operator_bytes_phase)
+    comp.use_device_kernel(S)                                        # a good state still works
+    assert [l[0] for l in comp.launches()][-2:] == ["s2n_leaf", "l2l"]
