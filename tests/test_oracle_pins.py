@@ -428,3 +428,109 @@ def test_planted_mistakes_fail_a_pin(monkeypatch):
     c2 = compress.compress(K, 256, leaf_size=32, max_rank=256, tol=0.0, kappa=8, budget=0.0, seed=4)
     c2.far[1] = np.zeros(0, dtype=np.int64)        # a dropped far pair
     assert not np.allclose(evaluate.tree_walk(c2, K, W), Kd @ W, rtol=1e-6, atol=1e-6)
+
+
+# ------------------------------------------------------------------ row samples (reading R10)
+def test_sample_rows_hand_example_neighbours_first():
+    """Hand-worked: members {2, 5, 7} of N = 20, kappa = 4.  Outside the node,
+    index 9 gets 3 votes, 3 and 11 get 2 each; |I'| = min(20 - 3, 2 * 3) = 6,
+    at most half (3) from the neighbours by (-votes, index): [9, 3, 11], then 3
+    distinct uniform draws from the rest of the complement."""
+    knn = np.tile(np.arange(20)[:, None], (1, 4))
+    knn[2] = [2, 9, 11, 5]
+    knn[5] = [5, 9, 3, 11]
+    knn[7] = [7, 3, 9, 2]
+    members = np.array([2, 5, 7])
+    for seed in range(20):
+        rows = compress.sample_rows(members, knn, 20, 3, np.random.default_rng(seed))
+        assert len(rows) == 6
+        assert list(rows[:3]) == [9, 3, 11]
+        rest = rows[3:]
+        assert len(set(rows.tolist())) == 6
+        assert not set(rest.tolist()) & {2, 5, 7, 9, 3, 11}
+        assert list(rest) == sorted(rest)
+
+
+def test_sample_rows_invariants_by_brute_force():
+    """Random neighbour lists: rows lie outside the node, are distinct, number
+    min(N - |a|, 2 ncols), and start with the ceil-free half of the outside
+    neighbours ranked by a vote count taken here with a plain loop."""
+    rng = np.random.default_rng(3)
+    n, kappa = 60, 5
+    knn = np.column_stack([np.arange(n), rng.integers(0, n, size=(n, kappa - 1))])
+    for trial in range(40):
+        size = int(rng.integers(1, 40))
+        members = np.sort(rng.choice(n, size=size, replace=False))
+        ncols = int(rng.integers(1, 30))
+        rows = compress.sample_rows(members, knn, n, ncols, np.random.default_rng(trial))
+        ns = min(n - size, 2 * ncols)
+        assert len(rows) == ns
+        assert len(set(rows.tolist())) == ns
+        assert not set(rows.tolist()) & set(members.tolist())
+        votes = {}
+        for i in members:
+            for j in knn[i]:
+                if j not in set(members.tolist()):
+                    votes[int(j)] = votes.get(int(j), 0) + 1
+        ranked = sorted(votes, key=lambda j: (-votes[j], j))
+        head = ranked[:ns // 2]
+        assert list(rows[:len(head)]) == head
+
+
+def test_sample_rows_whole_complement_and_uniform_fill():
+    """When 2 ncols reaches N - |a| the sample is the whole complement; the
+    uniform part draws every free index about equally often."""
+    knn = np.array([[i, (i + 1) % 6] for i in range(6)])
+    rows = compress.sample_rows(np.array([0, 1, 2, 3]), knn, 6, 4, np.random.default_rng(0))
+    assert sorted(rows.tolist()) == [4, 5] and rows[0] == 4          # 4 is 3's neighbour
+    n = 40
+    knn = np.tile(np.arange(n)[:, None], (1, 2))                       # no outside neighbours
+    counts = np.zeros(n)
+    for seed in range(2000):
+        rows = compress.sample_rows(np.array([0]), knn, n, 2, np.random.default_rng(seed))
+        counts[rows] += 1
+    assert counts[0] == 0
+    free = counts[1:]
+    assert free.sum() == 2000 * 4
+    expect = 2000 * 4 / 39
+    assert np.all(np.abs(free - expect) < 5 * np.sqrt(expect))
+
+
+# ------------------------------------------------------------------ eps_2 (Sec. 3)
+def test_eps2_hand_value():
+    exact = np.array([[1.0, 2.0], [3.0, 5.0]])
+    approx = np.array([[1.0, 2.0], [3.0, 4.0]])
+    assert dense.eps2(approx, exact) == pytest.approx(1.0 / math.sqrt(39.0), rel=1e-15)
+    assert dense.eps2(exact, exact) == 0.0
+    assert dense.eps2(2.0 * approx, 2.0 * exact) == pytest.approx(1.0 / math.sqrt(39.0), rel=1e-15)
+    assert dense.eps2(np.zeros((2, 2)), exact) == 1.0
+
+
+# ------------------------------------------------------------------ Table 2 flop count
+def test_algorithmic_flops_hss_closed_form():
+    """HSS (budget 0) on N = m 2^D with every rank forced to s (tau = 0): Table 2
+    gives per right-hand side N2S = 2 m s L + 2 s (2 s)(L - 2), S2S = 2 s^2 (2L - 2)
+    (the far pairs are the 2L - 2 sibling pairs), S2N = N2S, L2L = 2 m^2 L."""
+    m, s, D, r = 32, 8, 3, 3
+    L = 1 << D
+    n = m * L
+    K = _small_kernel(n, 3, "laplace_like", 1.0, 1e-2)
+    c = compress.compress(K, n, leaf_size=m, max_rank=s, tol=0.0, kappa=8, budget=0.0, seed=2)
+    assert all(c.rank(h) == s for h in range(1, c.nn))
+    assert sum(len(f) for f in c.far) == 2 * L - 2
+    n2s = 2 * m * s * L + 2 * s * (2 * s) * (L - 2)
+    closed = r * (2 * n2s + 2 * s * s * (2 * L - 2) + 2 * m * m * L)
+    assert evaluate.algorithmic_flops(c, r) == closed
+
+
+def test_algorithmic_flops_all_near_closed_form():
+    """Every leaf near every other (kappa = N): no far pairs, L2L is the dense
+    product 2 N^2 r, and N2S/S2N keep their HSS counts."""
+    m, s, D, r = 16, 4, 2, 5
+    L = 1 << D
+    n = m * L
+    K = _small_kernel(n, 2, "gaussian", 0.5, 1e-3)
+    c = compress.compress(K, n, leaf_size=m, max_rank=s, tol=0.0, kappa=n, budget=1.0, seed=3)
+    assert all(len(f) == 0 for f in c.far) and all(len(x) == L for x in c.near)
+    n2s = 2 * m * s * L + 2 * s * (2 * s) * (L - 2)
+    assert evaluate.algorithmic_flops(c, r) == r * (2 * n2s + 2 * n * n)
