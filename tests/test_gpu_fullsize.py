@@ -5,8 +5,12 @@ sampled rows at r=512, the N=262144 inverse multiquadric on 64 sampled rows
 at r=1024 (FP32 and split BF16), and eight of the batched instances in one
 persistent launch.
 
-Tolerances: FP32 1e-5 relative (Frobenius over the rows checked) against the
-oracle's FP64 walk of the same compression; split BF16 3e-5; the error
+Tolerances: FP32 1e-5 relative (Frobenius over the rows checked) and
+1e-5 x max|U| per element against the oracle's FP64 walk of the same
+compression; split BF16 3e-5 Frobenius and 1e-4 per element against that
+walk, and 1e-5 / 1e-5 against the oracle's walk with the operands rounded as
+stored (oracle/stored.py); plain BF16 P and coupling blocks (near blocks
+FP32) within the per-element allowance of that stored-form walk.  The error
 against the exact K W (eps_2 of Sec. 3) is stated and held to 1e-4 where the
 workload targets it.
 """
@@ -18,9 +22,14 @@ import pytest
 
 import workloads
 from gpu_util import export_read, log, rel_err
-from oracle import cfile, dense, evaluate, kernels
+from oracle import cfile, dense, evaluate, kernels, stored
 
 pytestmark = pytest.mark.gpu
+
+
+def _elem(got, ref):
+    """Largest element difference relative to max|ref|."""
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
 
 
 def _gpu_rhs(torch, w):
@@ -66,13 +75,20 @@ def test_clustered_gaussian_sampled_rows():
         for _ in range(3):                         # repeated evaluates in the timed configuration
             comp.evaluate(W, U)
         torch.cuda.synchronize()
+        c = export_read(comp)
         if ref is None:
-            ref = evaluate.tree_walk(export_read(comp), K, W64, rows)
-        got = U.cpu().numpy()[rows]
+            ref = evaluate.tree_walk(c, K, W64, rows)
+        got = U.cpu().numpy()[rows].astype(np.float64)
         e = rel_err(got, ref)
+        em = _elem(got, ref)
         eps = rel_err(got, exact)
-        log(f"  {name}: vs oracle {e:.2e}, eps2 vs exact {eps:.2e}")
-        assert e <= tol and eps <= 1e-4
+        log(f"  {name}: vs oracle {e:.2e} (element {em:.2e}), eps2 vs exact {eps:.2e}")
+        assert e <= tol and em <= (1e-5 if name == "fp32" else 1e-4) and eps <= 1e-4
+        if name == "bf16x3":
+            want = stored.tree_walk_stored(c, K, W64, "bf16x3", rows=rows)
+            es, ems = rel_err(got, want), _elem(got, want)
+            log(f"  {name}: vs stored-form oracle {es:.2e} (element {ems:.2e})")
+            assert es <= 1e-5 and ems <= 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -91,6 +107,8 @@ def large():
     rows = workloads.sample_rows(w.n, 64, w.seed)
     yield g, w, S, comp, c, K, rows, path
     os.unlink(path)
+    if os.path.exists(path + ".ref.npy"):
+        os.unlink(path + ".ref.npy")
 
 
 def test_large_imq_fp32_sampled_rows(large):
@@ -101,10 +119,11 @@ def test_large_imq_fp32_sampled_rows(large):
     U = comp.autotune(W)
     torch.cuda.synchronize()
     ref = evaluate.tree_walk(c, K, W64, rows)
-    got = U.cpu().numpy()[rows]
+    got = U.cpu().numpy()[rows].astype(np.float64)
     e = rel_err(got, ref)
-    log(f"  vs oracle {e:.2e}")
-    assert e <= 1e-5
+    em = _elem(got, ref)
+    log(f"  vs oracle {e:.2e} (element {em:.2e})")
+    assert e <= 1e-5 and em <= 1e-5
     np.save(path + ".ref.npy", ref)
     comp.free()
     torch.cuda.empty_cache()
@@ -120,15 +139,46 @@ def test_large_imq_split_bf16_sampled_rows(large):
     torch.cuda.synchronize()
     ref_file = path + ".ref.npy"
     ref = np.load(ref_file) if os.path.exists(ref_file) else evaluate.tree_walk(c, K, W64, rows)
-    got = U.cpu().numpy()[rows]
+    got = U.cpu().numpy()[rows].astype(np.float64)
     e = rel_err(got, ref)
+    em = _elem(got, ref)
     eps = rel_err(got, dense.kw(K, W64, rows))
-    log(f"  vs oracle {e:.2e}, eps2 vs exact {eps:.2e}")
-    assert e <= 3e-5 and eps <= 1e-4
+    log(f"  vs oracle {e:.2e} (element {em:.2e}), eps2 vs exact {eps:.2e}")
+    assert e <= 3e-5 and em <= 1e-4 and eps <= 1e-4
     c3.free()
     torch.cuda.empty_cache()
-    if os.path.exists(ref_file):
-        os.unlink(ref_file)
+
+
+def test_large_imq_bf16_far_fp32_near_sampled_rows(large):
+    """Plain BF16 P and coupling blocks with FP32 near blocks on the N=262144
+    compression (r = 1024, 64 sampled rows): every element within the
+    allowance of the oracle's walk with the operands rounded as stored; the
+    storage error against the FP64 walk and the exact K W is stated."""
+    import time
+    import torch
+    g, w, S, comp, c, K, rows, path = large
+    log(f"case {w.name} r={w.r} bf16 far / fp32 near, 64 sampled rows")
+    cb = g.Compression.load(path, S, storage=g.BF16, near_storage=g.FP32)
+    W, W64 = _gpu_rhs(torch, w)
+    U = cb.autotune(W)
+    torch.cuda.synchronize()
+    got = U.cpu().numpy()[rows].astype(np.float64)
+    del U
+    cb.free()
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    want = stored.tree_walk_stored(c, K, W64, "bf16", "fp32", rows=rows)
+    allow = stored.bf16_allowance(c, K, W64, near_storage="fp32", rows=rows)
+    diff = np.abs(got - want)
+    log(f"  stored-form oracle and allowance {time.perf_counter() - t0:.1f} s; vs stored {rel_err(got, want):.2e}, "
+        f"max diff / allowance {float(np.max(diff / np.maximum(allow, 1e-300))):.3f}, "
+        f"max allowance / max|U| {float(allow.max() / np.abs(want).max()):.2e}")
+    assert np.all(diff <= allow) and rel_err(got, want) <= 1e-3
+    ref_file = path + ".ref.npy"
+    ref = np.load(ref_file) if os.path.exists(ref_file) else evaluate.tree_walk(c, K, W64, rows)
+    log(f"  storage error: vs FP64 oracle {rel_err(got, ref):.2e}, eps2 vs exact "
+        f"{rel_err(got, dense.kw(K, W64, rows)):.2e}")
+    assert rel_err(got, ref) <= 2e-2
 
 
 def test_batched_instances_subset():
@@ -178,11 +228,12 @@ def test_large_imq_r2048_fp32_and_split_bf16(large):
         cc = g.Compression.load(path, S, storage=prec, near_storage=prec)
         U = cc.autotune(W)
         torch.cuda.synchronize()
-        got = U.cpu().numpy()[rows]
+        got = U.cpu().numpy()[rows].astype(np.float64)
         e = rel_err(got, ref)
+        em = _elem(got, ref)
         eps = rel_err(got, exact)
-        log(f"  {name}: vs oracle {e:.2e}, eps2 vs exact {eps:.2e}")
-        assert e <= tol and eps <= 1e-4
+        log(f"  {name}: vs oracle {e:.2e} (element {em:.2e}), eps2 vs exact {eps:.2e}")
+        assert e <= tol and em <= (1e-5 if name == "fp32" else 1e-4) and eps <= 1e-4
         del U
         cc.free()
         torch.cuda.empty_cache()
