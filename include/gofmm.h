@@ -192,6 +192,31 @@ int gofmm_evaluate(gofmm_compression* c, int64_t r,
                    void* hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as gofmm_evaluate, with the same kernels and the same bits, whose
+ * skeleton workspace (w~ and u~ rows) and work-item lists live in a fixed
+ * device array of the library, GOFMM_SCRATCH_BYTES bytes per device, held
+ * from the first such call on a device until the process ends.  The call
+ * allocates and frees no device memory: c must already be on the current
+ * device (gofmm_prepare, or any earlier evaluate there); it copies the work
+ * items into the array (one asynchronous host-to-device copy on hip_stream)
+ * and enqueues the launches.  Every call on a device shares the one array:
+ * calls that overlap on a device (different streams not ordered by the
+ * caller, or several threads) race and give wrong results; calls on one
+ * stream are ordered.  The opt-in persistent tree passes (GOFMM_PASSES) are
+ * not used here.  Argument rules as for gofmm_evaluate.  Errors: GOFMM_EINVAL
+ * also when c is not on the device yet; GOFMM_ELIMIT when the workspace for
+ * r (2 sum_a s_a rows of r FP32 values, r rounded up to a multiple of 4) and
+ * the work items exceed GOFMM_SCRATCH_BYTES (use a smaller r or
+ * gofmm_evaluate); GOFMM_EHIP for a failed copy or launch.
+ */
+#define GOFMM_SCRATCH_BYTES (256ll << 20)
+int gofmm_evaluate_noalloc(gofmm_compression* c, int64_t r,
+                           const float* W, int64_t ldw, float* U, int64_t ldu,
+                           void* hip_stream);
+
+/*
  * Same product as gofmm_evaluate, after timing every tile configuration of
  * every launch for this r and keeping the fastest (later evaluates with the
  * same r reuse the choice).  Each configuration is timed inside whole

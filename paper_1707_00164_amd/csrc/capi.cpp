@@ -13,6 +13,7 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 void device_prepare(Compression& c, i64 r_max);
 void device_evaluate(Compression& c, i64 r, const float* W, i64 ldw, float* U, i64 ldu, void* stream);
+void device_evaluate_noalloc(Compression& c, i64 r, const float* W, i64 ldw, float* U, i64 ldu, void* stream);
 void device_autotune(Compression& c, i64 r, const float* W, i64 ldw, float* U, i64 ldu, void* stream, int reps);
 void device_evaluate_batched(int k, Compression* const* c, const i64* r, const float* const* W,
                              const i64* ldw, float* const* U, const i64* ldu, void* stream);
@@ -177,6 +178,15 @@ extern "C" int gofmm_evaluate(gofmm_compression* c, int64_t r, const float* W, i
     check_eval(c, r, W, ldw, U, ldu);
     if (r == 0) return;
     device_evaluate(c->c, r, W, ldw, U, ldu, hip_stream);
+  });
+}
+
+extern "C" int gofmm_evaluate_noalloc(gofmm_compression* c, int64_t r, const float* W, int64_t ldw, float* U,
+                                      int64_t ldu, void* hip_stream) {
+  return guarded([&] {
+    check_eval(c, r, W, ldw, U, ldu);
+    if (r == 0) return;
+    device_evaluate_noalloc(c->c, r, W, ldw, U, ldu, hip_stream);
   });
 }
 

@@ -109,6 +109,15 @@ struct DeviceState {
     unsigned long long epoch = 0, head_base = 0;
   };
   std::map<std::tuple<int, int, i64>, Pass> passes;
+  // allocation-free evaluate: per (r, configuration of every launch), the
+  // work items of all launches back to back in host memory (never modified
+  // once built, so an asynchronous copy may read them), with each launch's
+  // (offset, count)
+  struct FixedItems {
+    std::vector<int2> items;
+    std::vector<std::pair<size_t, int>> at;
+  };
+  std::map<std::vector<i64>, FixedItems> fixed;
   i64 op_bytes = 0;
   // per-launch timing (HIP events around every launch while enabled)
   bool profiling = false;
@@ -441,12 +450,15 @@ struct EvalArgs {
   hipStream_t stream;
 };
 
-static bool make_args(Compression& c, int li, int cfg, const EvalArgs& e, dev::KArgs& a, int& grid) {
+// Kernel arguments of launch li; `fixed_items` and `fixed_ws` replace the
+// library-allocated work items and workspace (the allocation-free evaluate).
+static bool make_args(Compression& c, int li, int cfg, const EvalArgs& e, dev::KArgs& a, int& grid,
+                      const std::pair<int2*, int>* fixed_items = nullptr, float* fixed_ws = nullptr) {
   DeviceState* d = c.dev;
   const LaunchDesc& l = c.plan.launches[li];
   const Cfg& g = kCfgs[cfg];
   const int ntn = (int)((e.r + g.bn - 1) / g.bn);
-  auto it = items_for(c, li, cfg, ntn);
+  auto it = fixed_items ? *fixed_items : items_for(c, li, cfg, ntn);
   if (it.second == 0) return false;
   a.tasks = d->tasks;
   a.items = it.first;
@@ -466,7 +478,7 @@ static bool make_args(Compression& c, int li, int cfg, const EvalArgs& e, dev::K
   a.ldw = e.ldw;
   a.U = e.U;
   a.ldu = e.ldu;
-  a.WS = d->ws;
+  a.WS = fixed_ws ? fixed_ws : d->ws;
   a.ldws = ws_cols_for(e.r);
   a.r = (int)e.r;
   a.vec = ((uintptr_t)e.W % 16 == 0) && ((uintptr_t)e.U % 16 == 0) && e.ldw % 4 == 0 && e.ldu % 4 == 0 && e.r % 4 == 0;
@@ -688,6 +700,87 @@ void device_evaluate(Compression& c, i64 r, const float* W, i64 ldw, float* U, i
   if (c.dev->device != cur) fail(GOFMM_EINVAL, "current device differs from the compression's device");
   if (r > INT32_MAX / 2) fail(GOFMM_ELIMIT, "r too large");
   launch_all(c, EvalArgs{r, W, ldw, U, ldu, (hipStream_t)stream});
+}
+
+// ------------------------------------------------------------------ allocation-free evaluate
+// For callers that cannot allocate device memory (code under graph capture,
+// tight serving loops): the skeleton workspace (w~ and u~ rows) and the work
+// items of one evaluate live in `scratch`, a fixed array of every device the
+// library runs on, instead of library allocations.  Each device keeps its copy
+// until the process ends; every call on a device shares it and leaves its
+// contents behind.  Nothing in it needs to start at zero: every workspace row
+// is written (S2S, N2S) before it is read or accumulated into, and the work
+// items are copied in by each call.
+constexpr size_t kScratchBytes = (size_t)GOFMM_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy of the array at its own address).
+static unsigned char* scratch_on(int device) {
+  static std::mutex mu;
+  static std::map<int, unsigned char*> addr;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  void* p = nullptr;
+  HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) fail(GOFMM_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+  addr[device] = static_cast<unsigned char*>(p);
+  return addr[device];
+}
+
+static size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+void device_evaluate_noalloc(Compression& c, i64 r, const float* W, i64 ldw, float* U, i64 ldu, void* stream) {
+  if (!c.dev) fail(GOFMM_EINVAL, "the compression is not on the device: call gofmm_prepare first");
+  int cur;
+  HIP_OK(hipGetDevice(&cur));
+  if (c.dev->device != cur) fail(GOFMM_EINVAL, "current device differs from the compression's device");
+  if (r > INT32_MAX / 2) fail(GOFMM_ELIMIT, "r too large");
+  const HostPlan& pl = c.plan;
+  const int nl = (int)pl.launches.size();
+  std::vector<i64> key(nl + 1);
+  key[0] = r;
+  for (int li = 0; li < nl; ++li) key[li + 1] = cfg_for(c, li, r);
+  DeviceState* d = c.dev;
+  auto fit = d->fixed.find(key);
+  if (fit == d->fixed.end()) {
+    DeviceState::FixedItems f;
+    for (int li = 0; li < nl; ++li) {
+      const Cfg& g = kCfgs[key[li + 1]];
+      const int ntn = (int)((r + g.bn - 1) / g.bn);
+      if (ntn >= (1 << 16)) fail(GOFMM_ELIMIT, "too many column tiles");
+      const LaunchDesc& l = pl.launches[li];
+      for (i32 k = l.t_begin; k < l.t_end; ++k)
+        if ((pl.tasks[k].m + g.bm - 1) / g.bm >= (1 << 15)) fail(GOFMM_ELIMIT, "too many row tiles");
+      std::vector<int2> v = build_items(pl, l, g.bm, ntn);
+      f.at.push_back({f.items.size(), (int)v.size()});
+      f.items.insert(f.items.end(), v.begin(), v.end());
+    }
+    fit = d->fixed.emplace(key, std::move(f)).first;
+  }
+  const DeviceState::FixedItems& f = fit->second;
+  const size_t ws_bytes = round256((size_t)std::max<i64>(1, pl.ws_rows) * (size_t)ws_cols_for(r) * sizeof(float));
+  const size_t it_bytes = f.items.size() * sizeof(int2);
+  if (ws_bytes + it_bytes > kScratchBytes)
+    fail(GOFMM_ELIMIT, "this evaluate needs " + std::to_string(ws_bytes + it_bytes) +
+                           " bytes of scratch; the fixed array holds " + std::to_string(kScratchBytes) +
+                           " (use a smaller r, or gofmm_evaluate)");
+  unsigned char* base = scratch_on(cur);
+  float* ws = reinterpret_cast<float*>(base);
+  int2* items = reinterpret_cast<int2*>(base + ws_bytes);
+  const hipStream_t st = (hipStream_t)stream;
+  if (it_bytes) HIP_OK(hipMemcpyAsync(items, f.items.data(), it_bytes, hipMemcpyHostToDevice, st));
+  const EvalArgs e{r, W, ldw, U, ldu, st};
+  for (int li = 0; li < nl; ++li) {
+    const int cfg = (int)key[li + 1];
+    const std::pair<int2*, int> fi{items + f.at[li].first, f.at[li].second};
+    dev::KArgs a;
+    int grid = 0;
+    if (!make_args(c, li, cfg, e, a, grid, &fi, ws)) continue;
+    hipLaunchKernelGGL(kernel_for(c, pl.launches[li], cfg, a.vec != 0), dim3(grid), dim3(kCfgs[cfg].nt), 0, st, a);
+    HIP_OK(hipGetLastError());
+  }
 }
 
 // Time every configuration of every segment for this r and keep the fastest.

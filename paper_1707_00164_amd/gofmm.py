@@ -69,6 +69,8 @@ SIGNATURES = [
     ("gofmm_export", C.c_int, [C.c_void_p, C.c_char_p]),
     ("gofmm_prepare", C.c_int, [C.c_void_p, C.c_int64]),
     ("gofmm_evaluate", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
+    ("gofmm_evaluate_noalloc", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                         C.c_void_p]),
     ("gofmm_autotune", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     ("gofmm_evaluate_batched", C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
@@ -293,6 +295,13 @@ class Compression:
             U = torch.empty_like(W, memory_format=torch.contiguous_format)
         _check(lib().gofmm_evaluate(self.h, W.shape[1], _ptr(W), W.stride(0), _ptr(U), U.stride(0),
                                     _stream(stream)))
+        return U
+
+    def evaluate_noalloc(self, W, U, stream=None):
+        """U = K~ W with the workspace in the library's fixed scratch array
+        (no device allocation; the compression must already be on the device)."""
+        _check(lib().gofmm_evaluate_noalloc(self.h, W.shape[1], _ptr(W), W.stride(0), _ptr(U), U.stride(0),
+                                            _stream(stream)))
         return U
 
     def autotune(self, W, U=None, stream=None):

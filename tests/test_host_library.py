@@ -234,6 +234,9 @@ def test_error_codes(g):
         g.Compression.load("/nonexistent/file", S)
     assert e.value.code == -6
     L.gofmm_free(None)
+    # the allocation-free evaluate needs the compression on the device first
+    assert L.gofmm_evaluate_noalloc(comp.h, 4, 4096, 4, 1 << 20, 4, None) == -1
+    assert L.gofmm_evaluate_noalloc(None, 4, 4096, 4, 1 << 20, 4, None) == -1
 
 
 def test_footprint_grows_with_r(small):
