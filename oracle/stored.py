@@ -18,7 +18,14 @@ operands rounded the way the form defines them and every sum taken in FP64:
 A is P (N2S, S2N at every level), a coupling block K(b~, a~) (S2S) or a near
 block K(b, a) (L2L).  P and coupling blocks use the `storage` form, near
 blocks the `near_storage` form.  The intermediate w~ and u~ are carried in
-FP64 between the steps; only the operand of each product is rounded.
+FP64 between the steps by default; only the operand of each product is
+rounded.  With carry="fp32" every intermediate is rounded to FP32 where a
+device keeps it in an FP32 workspace: w~ of a node once formed, u~ of a node
+once its far-field sum is formed, and again after each parent's S2N
+contribution is added (the sums themselves stay in FP64).  Plain BF16 needs
+this reading to be compared element by element: its BF16 rounding of an
+intermediate amplifies any difference in the value rounded, and FP64 against
+FP32 intermediates differ enough to flip many roundings up a deep tree.
 
 BF16 here is the IEEE-style binary format with 8 significant bits and the
 exponent range of FP32 (subnormals included), rounded to nearest with ties to
@@ -101,9 +108,13 @@ def _wanted(c: Compression, rows):
 
 
 def tree_walk_stored(c: Compression, K, W: np.ndarray, storage: str, near_storage: Optional[str] = None,
-                     rows: Optional[np.ndarray] = None) -> np.ndarray:
-    """Rows `rows` (default all) of K~ W, each product in its storage form."""
+                     rows: Optional[np.ndarray] = None, carry: str = "fp64") -> np.ndarray:
+    """Rows `rows` (default all) of K~ W, each product in its storage form;
+    intermediates carried in FP64 or, with carry="fp32", rounded to FP32."""
     near_storage = storage if near_storage is None else near_storage
+    if carry not in ("fp64", "fp32"):
+        raise ValueError(carry)
+    keep = fp32 if carry == "fp32" else (lambda x: x)
     W = np.asarray(W, dtype=np.float64)
     r = W.shape[1]
     fl = first_leaf(c.depth)
@@ -113,9 +124,9 @@ def tree_walk_stored(c: Compression, K, W: np.ndarray, storage: str, near_storag
     for h in range(c.nn - 1, 0, -1):
         if h >= fl:
             a = int(c.node_start[h])
-            wt[h] = product(c.proj[h], Wp[a:a + int(c.node_size[h])], storage)
+            wt[h] = keep(product(c.proj[h], Wp[a:a + int(c.node_size[h])], storage))
         else:
-            wt[h] = product(c.proj[h], np.vstack([wt[2 * h + 1], wt[2 * h + 2]]), storage)
+            wt[h] = keep(product(c.proj[h], np.vstack([wt[2 * h + 1], wt[2 * h + 2]]), storage))
     want_leaf, want = _wanted(c, rows)
     # S2S
     ut: List[Optional[np.ndarray]] = [None] * c.nn
@@ -125,7 +136,7 @@ def tree_walk_stored(c: Compression, K, W: np.ndarray, storage: str, near_storag
             for a in c.far[h]:
                 a = int(a)
                 acc += product(K(c.skel[h], c.skel[a]), wt[a], storage)
-        ut[h] = acc
+        ut[h] = keep(acc)
     # S2N (PRE: heap order visits a parent before its children)
     Up = np.zeros((c.n, r))
     for h in range(1, c.nn):
@@ -137,8 +148,8 @@ def tree_walk_stored(c: Compression, K, W: np.ndarray, storage: str, near_storag
         else:
             d = product(c.proj[h].T, ut[h], storage)
             sl = c.rank(2 * h + 1)
-            ut[2 * h + 1] = ut[2 * h + 1] + d[:sl]
-            ut[2 * h + 2] = ut[2 * h + 2] + d[sl:]
+            ut[2 * h + 1] = keep(ut[2 * h + 1] + d[:sl])
+            ut[2 * h + 2] = keep(ut[2 * h + 2] + d[sl:])
     # L2L
     for b in np.flatnonzero(want_leaf):
         h = fl + int(b)

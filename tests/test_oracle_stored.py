@@ -200,3 +200,81 @@ def test_sampled_rows_equal_the_full_walk():
         assert np.array_equal(stored.tree_walk_stored(c, Kk, W, form, rows=rows),
                               stored.tree_walk_stored(c, Kk, W, form)[rows])
     assert np.array_equal(stored.bf16_allowance(c, Kk, W, rows=rows), stored.bf16_allowance(c, Kk, W)[rows])
+
+
+@pytest.mark.parametrize("name", sorted(grid_cases.CASES))
+def test_fp32_carry_is_exact_on_integer_grids(name):
+    """Integer intermediates below 2^24 are FP32 values: carrying them in FP32
+    changes nothing in any form."""
+    c, A, K, W = _walks(name)
+    for form in ("fp32", "bf16", "bf16x3"):
+        assert np.array_equal(stored.tree_walk_stored(c, K, W, form, carry="fp32"),
+                              stored.tree_walk_stored(c, K, W, form))
+
+
+def test_depth_one_hss_bf16_fp32_carry_step_by_step():
+    """Two leaves, HSS, plain BF16 P and coupling blocks, FP32 near blocks,
+    FP32 intermediates: w~ and u~ rounded to FP32 once formed, each rounded to
+    BF16 (by torch, from its FP32 value) as an operand."""
+    import torch
+
+    def tb(x):
+        return torch.from_numpy(np.asarray(x, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+    def f32(x):
+        return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+    rng = np.random.default_rng(6)
+    n = 200
+    Kk = kernels.KernelMatrix(rng.random((n, 2)), "gaussian", 0.4, 1e-2)
+    c = compress.compress(Kk, n, leaf_size=100, max_rank=12, tol=1e-7, kappa=4, budget=0.0, seed=3)
+    assert c.depth == 1
+    W = workloads.rhs(n, 3, 7).astype(np.float32).astype(np.float64)
+    Wp = W[c.perm]
+    rows = {h: slice(int(c.node_start[h]), int(c.node_start[h] + c.node_size[h])) for h in (1, 2)}
+    ba = stored.bf16                  # stored operators: BF16 of the FP64 value (pinned above)
+    wt = {h: f32(ba(c.proj[h]) @ tb(Wp[rows[h]])) for h in (1, 2)}
+    ut = {1: f32(ba(Kk(c.skel[1], c.skel[2])) @ tb(wt[2])), 2: f32(ba(Kk(c.skel[2], c.skel[1])) @ tb(wt[1]))}
+    Up = np.zeros_like(Wp)
+    for h in (1, 2):
+        Up[rows[h]] = (ba(c.proj[h]).T @ tb(ut[h]) +
+                       Kk(c.indices(h), c.indices(h)).astype(np.float32).astype(np.float64) @ Wp[rows[h]])
+    want = np.empty_like(Up)
+    want[c.perm] = Up
+    got = stored.tree_walk_stored(c, Kk, W, "bf16", "fp32", carry="fp32")
+    assert np.allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+    # the carry is live: split BF16 reads the low bits of each intermediate
+    assert not np.array_equal(stored.tree_walk_stored(c, Kk, W, "bf16x3", carry="fp32"),
+                              stored.tree_walk_stored(c, Kk, W, "bf16x3"))
+
+
+def test_plain_bf16_is_sensitive_to_fp32_level_differences():
+    """Why plain BF16 is compared element by element only on exact (integer)
+    inputs: each intermediate is rounded to 8 significant bits before it is
+    used, so a difference of a few FP32 units in the sums that form it (a
+    different accumulation order) flips some of those roundings, and the
+    flips compound up the tree.  Two walks that differ only by such noise
+    differ by far more than FP32 roundoff, though by less than one BF16 unit
+    (2^-8) and less than the form's own storage error."""
+    rng = np.random.default_rng(1)
+    n = 3000
+    Kk = kernels.KernelMatrix(rng.random((n, 4)), "imq", 0.3, 1e-2)
+    c = compress.compress(Kk, n, leaf_size=96, max_rank=96, tol=1e-6, kappa=16, budget=0.03, seed=1)
+    W = workloads.rhs(n, 8, 2).astype(np.float32).astype(np.float64)
+    ref = stored.tree_walk_stored(c, Kk, W, "bf16", "fp32", carry="fp32")
+    real = stored.product
+    noise = np.random.default_rng(5)
+
+    def perturbed(A, B, form):
+        out = real(A, B, form)
+        s = np.abs(stored.bf16(A)) @ np.abs(stored.bf16(B))
+        return out + s * 4 * 2.0 ** -24 * noise.uniform(-1, 1, size=out.shape)
+
+    try:
+        stored.product = perturbed
+        sim = stored.tree_walk_stored(c, Kk, W, "bf16", "fp32", carry="fp32")
+    finally:
+        stored.product = real
+    d = np.linalg.norm(sim - ref) / np.linalg.norm(ref)
+    storage = np.linalg.norm(ref - stored.tree_walk_stored(c, Kk, W, "fp32")) / np.linalg.norm(ref)
+    assert 1e-5 < d < min(2.0 ** -8, storage)
