@@ -90,6 +90,15 @@ typedef struct {
   int32_t ann_max_iters;    /* randomized trees for the neighbour search (10) */
   double ann_target_recall; /* stop the neighbour search at this recall (0.8) */
   int32_t exact_knn;        /* 1: brute-force neighbours instead (small N) */
+  int32_t device_knn;       /* 1: merge the neighbour candidates on the current
+                               HIP device (the ANN task of Table 2: each leaf's
+                               sampled block K(leaf, leaf), or a block of rows
+                               against every index for exact_knn, becomes FP64
+                               Gram distances, and every row keeps its kappa
+                               nearest by (distance, index)); same lists as the
+                               host, bit for bit.  Needs kappa <= 64 and
+                               n < 2^31; the host still samples every block.
+                               0 (default): everything on the host */
 } gofmm_params;
 
 /* Summary of a built compression (for flop/byte accounting and reports). */
@@ -274,6 +283,12 @@ int gofmm_batched_spin_limit(int64_t polls);
  * Wait for the device and report the persistent tree passes of c: *error = 1
  * if a block of one of its passes gave up a dependency wait since the last
  * call (the same bound as gofmm_batched_spin_limit), else 0.  Clears the flag.
+ * An evaluate returns before its launches run, so its return code cannot
+ * carry this: a wait that gives up skips its tile and the evaluate's output
+ * is wrong while the call itself returned GOFMM_OK.  Callers that enable the
+ * persistent passes (GOFMM_PASSES=1) must call this after their evaluates
+ * and discard the outputs of any evaluate it flags.  The default separate
+ * launches never wait and never set the flag.
  */
 int gofmm_evaluate_status(gofmm_compression* c, int32_t* error);
 
@@ -340,6 +355,11 @@ typedef struct {
   int64_t hbm_used, hbm_budget;
   double p50_ms, p99_ms, mean_ms, max_ms;   /* latency, submit to completion */
   double elapsed_ms;          /* since creation or the last reset */
+  int64_t max_inflight;       /* most batches on the device at once */
+  int64_t admissions;         /* models made resident */
+  double host_ms_mean;        /* host time to form and enqueue one batch */
+  double admit_ms_mean;       /* host time of one admission (upload, staging) */
+  double p99_ms_admitting;    /* p99 latency of requests finished while an admission ran */
 } gofmm_server_stats_t;
 
 /* Start a server with `streams` concurrent batches (1..16) on the current

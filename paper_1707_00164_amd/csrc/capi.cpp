@@ -61,6 +61,8 @@ static void check_params(const gofmm_params* p) {
     if (s != GOFMM_FP32 && s != GOFMM_BF16 && s != GOFMM_BF16X3) fail(GOFMM_EINVAL, "unknown storage precision");
   if (p->threads < 0) fail(GOFMM_EINVAL, "threads must be >= 0");
   if (!(p->ann_target_recall >= 0.0 && p->ann_target_recall <= 1.0)) fail(GOFMM_EINVAL, "ann_target_recall in [0,1]");
+  if (p->device_knn != 0 && p->device_knn != 1) fail(GOFMM_EINVAL, "device_knn must be 0 or 1");
+  if (p->device_knn && p->kappa > 64) fail(GOFMM_EINVAL, "device_knn keeps at most 64 neighbours");
 }
 
 extern "C" void gofmm_default_params(gofmm_params* p) {
@@ -79,6 +81,7 @@ extern "C" void gofmm_default_params(gofmm_params* p) {
   p->ann_max_iters = 10;
   p->ann_target_recall = 0.8;
   p->exact_knn = 0;
+  p->device_knn = 0;
 }
 
 extern "C" int gofmm_compress(int64_t n, gofmm_sampler sampler, void* user, const gofmm_params* params,

@@ -245,6 +245,55 @@ void exact_neighbours(const Dist& d, i64 n, const i64* rows, i64 nrows, int kapp
   });
 }
 
+// The sampled blocks K(rows, cols) of `sets`, merged into the device lists
+// in batches of at most kKnnBatch entries (each batch sampled on the host by
+// the compression's threads, one block per thread).
+struct KnnSet { const i64* rows; i64 nr; const i64* cols; i64 nc; };
+constexpr size_t kKnnBatch = (size_t)32 << 20;
+
+void knn_merge_sets(KnnDevice* kd, const Dist& d, const std::vector<KnnSet>& sets) {
+  size_t q = 0;
+  while (q < sets.size()) {
+    std::vector<KnnTask> tasks;
+    std::vector<int> idx;
+    size_t tot = 0;
+    const size_t q0 = q;
+    while (q < sets.size() && (q == q0 || tot + (size_t)(sets[q].nr * sets[q].nc) <= kKnnBatch)) {
+      const KnnSet& s = sets[q];
+      KnnTask t{(i64)tot, (i64)idx.size(), s.nr, 0, s.nc};
+      for (i64 a = 0; a < s.nr; ++a) idx.push_back((int)s.rows[a]);
+      if (s.cols == s.rows && s.nc == s.nr) {
+        t.cofs = t.rofs;
+      } else {
+        t.cofs = (i64)idx.size();
+        for (i64 a = 0; a < s.nc; ++a) idx.push_back((int)s.cols[a]);
+      }
+      tasks.push_back(t);
+      tot += (size_t)(s.nr * s.nc);
+      ++q;
+    }
+    std::vector<double> blocks(tot);
+    parallel_for((i64)tasks.size(), d.threads, [&](i64 t) {
+      const KnnSet& s = sets[q0 + t];
+      d.K(s.nr, s.rows, s.nc, s.cols, &blocks[tasks[t].kofs]);
+    });
+    knn_device_merge(kd, tasks, idx, blocks);
+  }
+}
+
+// Recall of the lists on the probes against their exact neighbours.
+double knn_recall(const Compression& c, const std::vector<i64>& probes, const std::vector<i64>& truth, int kappa) {
+  i64 hit = 0;
+  const i64 np = (i64)probes.size();
+  for (i64 t = 0; t < np; ++t) {
+    const i64* a = &c.knn[(size_t)probes[t] * kappa];
+    for (int u = 0; u < kappa; ++u)
+      for (int v = 0; v < kappa; ++v)
+        if (a[v] == truth[t * kappa + u]) { ++hit; break; }
+  }
+  return (double)hit / (double)(np * kappa);
+}
+
 void neighbours(Compression& c, const Dist& d, const gofmm_params& p) {
   const i64 n = c.n;
   const int kappa = (int)std::min<i64>(p.kappa, n);
@@ -252,6 +301,18 @@ void neighbours(Compression& c, const Dist& d, const gofmm_params& p) {
   c.knn.assign((size_t)n * kappa, -1);
   std::vector<i64> all(n);
   std::iota(all.begin(), all.end(), 0);
+  // device merges: the same trees, blocks and (distance, index) rule as the
+  // host path below, so the same lists
+  std::unique_ptr<KnnDevice, void (*)(KnnDevice*)> dev(nullptr, knn_device_free);
+  if (p.device_knn) dev.reset(knn_device_create(n, kappa, d.kind, d.diag.data()));
+  if (p.exact_knn && dev) {
+    const i64 R = std::max<i64>(1, std::min<i64>(64, (i64)(kKnnBatch / 4) / n));
+    std::vector<KnnSet> sets;
+    for (i64 r0 = 0; r0 < n; r0 += R) sets.push_back({&all[r0], std::min(R, n - r0), all.data(), n});
+    knn_merge_sets(dev.get(), d, sets);
+    knn_device_read(dev.get(), c.knn.data());
+    return;
+  }
   if (p.exact_knn) {
     exact_neighbours(d, n, all.data(), n, kappa, c.knn.data(), d.threads);
     return;
@@ -274,6 +335,14 @@ void neighbours(Compression& c, const Dist& d, const gofmm_params& p) {
           Rng rng(mix(mix(c.seed, 0xB0B + it), h));
           random_split(d, idx, rng, l, r);
         }, nullptr);
+    if (dev) {
+      std::vector<KnnSet> sets;
+      for (const auto& idx : leaves) sets.push_back({idx.data(), (i64)idx.size(), idx.data(), (i64)idx.size()});
+      knn_merge_sets(dev.get(), d, sets);
+      knn_device_read(dev.get(), c.knn.data());
+      if (knn_recall(c, probes, truth, kappa) >= p.ann_target_recall) break;
+      continue;
+    }
     parallel_for((i64)leaves.size(), d.threads, [&](i64 b) {
       const auto& idx = leaves[b];
       const i64 m = (i64)idx.size();
@@ -287,15 +356,7 @@ void neighbours(Compression& c, const Dist& d, const gofmm_params& p) {
         merge_list(&c.knn[(size_t)i * kappa], &kd[(size_t)i * kappa], kappa, cand);
       }
     });
-    i64 hit = 0;
-    for (i64 t = 0; t < np; ++t) {
-      const i64* a = &c.knn[(size_t)probes[t] * kappa];
-      for (int u = 0; u < kappa; ++u)
-        for (int v = 0; v < kappa; ++v)
-          if (a[v] == truth[t * kappa + u]) { ++hit; break; }
-    }
-    const double recall = (double)hit / (double)(np * kappa);
-    if (recall >= p.ann_target_recall) break;
+    if (knn_recall(c, probes, truth, kappa) >= p.ann_target_recall) break;
   }
 }
 

@@ -200,6 +200,17 @@ void read_file(Compression& c, const char* path);
 int interp_decomp(double* A, int nrow, int ncol, double tol, int smax,
                   std::vector<int>& piv, std::vector<double>& P);
 
+// Neighbour-list merges on the device (knn.hip).  A task is the sampled
+// block K(R, C), column-major with leading dimension nr, at blocks[kofs];
+// its rows are idx[rofs .. rofs + nr), its columns idx[cofs .. cofs + nc).
+struct KnnTask { i64 kofs, rofs, nr, cofs, nc; };
+struct KnnDevice;
+KnnDevice* knn_device_create(i64 n, int kappa, int kind, const double* diag);
+void knn_device_merge(KnnDevice* k, const std::vector<KnnTask>& tasks, const std::vector<int>& idx,
+                      const std::vector<double>& blocks);
+void knn_device_read(KnnDevice* k, i64* knn);       // n x kappa, -1 for an empty entry
+void knn_device_free(KnnDevice* k);
+
 // BF16 round-to-nearest-even of a double (through its nearest float).
 uint16_t to_bf16(double x);
 double from_bf16(uint16_t h);

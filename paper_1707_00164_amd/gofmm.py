@@ -31,7 +31,7 @@ class Params(C.Structure):
                 ("kappa", C.c_int32), ("budget", C.c_double), ("distance", C.c_int32),
                 ("storage", C.c_int32), ("near_storage", C.c_int32), ("seed", C.c_uint64),
                 ("threads", C.c_int32), ("ann_max_iters", C.c_int32),
-                ("ann_target_recall", C.c_double), ("exact_knn", C.c_int32)]
+                ("ann_target_recall", C.c_double), ("exact_knn", C.c_int32), ("device_knn", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -55,7 +55,9 @@ class ServerStats(C.Structure):
                 ("batches", C.c_int64), ("columns", C.c_int64), ("packed", C.c_int64),
                 ("hbm_used", C.c_int64), ("hbm_budget", C.c_int64),
                 ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
-                ("max_ms", C.c_double), ("elapsed_ms", C.c_double)]
+                ("max_ms", C.c_double), ("elapsed_ms", C.c_double), ("max_inflight", C.c_int64),
+                ("admissions", C.c_int64), ("host_ms_mean", C.c_double), ("admit_ms_mean", C.c_double),
+                ("p99_ms_admitting", C.c_double)]
 
 
 _lib = None

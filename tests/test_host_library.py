@@ -234,6 +234,20 @@ def test_error_codes(g):
         g.Compression.load("/nonexistent/file", S)
     assert e.value.code == -6
     L.gofmm_free(None)
+    # device neighbour merges: argument checks, and a clean failure without a GPU
+    for kw in (dict(device_knn=2), dict(device_knn=1, kappa=65)):
+        with pytest.raises(g.GofmmError) as e:
+            g.Compression.compress(S, leaf_size=8, **kw)
+        assert e.value.code == -1
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except ImportError:
+        has_gpu = False
+    if not has_gpu:
+        with pytest.raises(g.GofmmError) as e:
+            g.Compression.compress(S, leaf_size=8, device_knn=1)
+        assert e.value.code == -5
     # the allocation-free evaluate needs the compression on the device first
     assert L.gofmm_evaluate_noalloc(comp.h, 4, 4096, 4, 1 << 20, 4, None) == -1
     assert L.gofmm_evaluate_noalloc(None, 4, 4096, 4, 1 << 20, 4, None) == -1
