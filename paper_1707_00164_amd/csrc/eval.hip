@@ -203,7 +203,8 @@ void device_prepare(Compression& c, i64 r_max) {
   DeviceState* d = c.dev;
   const i64 cols = ws_cols_for(r_max);
   if (cols > d->ws_cols) {
-    HIP_OK(hipDeviceSynchronize());
+    // work in flight may still use the old workspace (a fresh state has none)
+    if (d->ws) HIP_OK(hipDeviceSynchronize());
     (void)hipFree(d->ws);
     d->ws = nullptr;
     d->ws_cols = 0;

@@ -72,6 +72,7 @@ struct Model {
   i64 r_max;
   i64 footprint;
   bool admitted = false;
+  bool admitting = false;   // its upload runs (outside the server lock)
   bool busy = false;
   bool removing = false;
   int prec = 0;
@@ -95,9 +96,10 @@ struct Server {
   std::vector<std::unique_ptr<BatchRing>> rings;
   std::vector<char> stream_busy;
   std::mutex mu;
-  std::condition_variable cv, done_cv;
-  bool stop = false;
-  std::thread th;
+  std::condition_variable cv, done_cv, admit_cv;
+  bool stop = false, stop_admit = false;
+  std::thread th, admitter;
+  int admit_job = 0;        // model whose upload the admission thread runs
   int next_model = 1;
   i64 next_req = 1;
   std::map<int, std::unique_ptr<Model>> models;
@@ -105,12 +107,16 @@ struct Server {
   std::map<i64, std::unique_ptr<Request>> reqs;
   std::vector<Flight> flights;
   std::vector<double> lat;
+  std::vector<double> lat_admitting;   // requests finished while an admission ran
   i64 completed = 0, failed = 0, batches = 0, columns = 0, packed = 0;
+  i64 max_inflight = 0, admissions = 0;
+  double host_ms = 0, admit_ms = 0;
   double t0 = now_ms(), busy_ms = 0;
   std::string fatal;
 
   void loop();
   void admit();
+  void admit_loop();
   void retire();
   bool launch_one();
   void release_model(Model& m);
@@ -128,11 +134,34 @@ void Server::release_model(Model& m) {
   m.admitted = false;
 }
 
-// Admit queued models, in order, while they fit the budget.
+// Admit queued models, in order, while they fit the budget.  The loop thread
+// only reserves the footprint and hands the model to the admission thread;
+// the upload (operator, tables, workspace, staging) runs there with the
+// server lock released, so batches keep being retired and launched and
+// requests keep arriving meanwhile.  The model is marked busy until its
+// upload ends, so a removal waits for it.  One admission at a time.
 void Server::admit() {
-  while (!admit_q.empty()) {
-    Model& m = *models[admit_q.front()];
-    if (used + m.footprint > budget) break;
+  if (admit_job || admit_q.empty()) return;
+  Model& m = *models[admit_q.front()];
+  if (used + m.footprint > budget) return;
+  admit_q.pop_front();
+  used += m.footprint;
+  m.admitting = m.busy = true;
+  admit_job = m.id;
+  admit_cv.notify_all();
+}
+
+void Server::admit_loop() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  while (true) {
+    admit_cv.wait(lk, [&] { return admit_job != 0 || stop_admit; });
+    if (!admit_job) break;
+    Model& m = *models[admit_job];
+    const double ta = now_ms();
+    std::string err;
+    bool ok = true;
+    lk.unlock();
     try {
       if (m.c->dev) {                 // drop any earlier device state: the server sizes it
         device_state_free(m.c->dev);
@@ -141,20 +170,31 @@ void Server::admit() {
       device_prepare(*m.c, m.r_max);
       SHIP_OK(hipMalloc((void**)&m.Wc, (size_t)m.c->n * m.r_max * sizeof(float)));
       SHIP_OK(hipMalloc((void**)&m.Uc, (size_t)m.c->n * m.r_max * sizeof(float)));
+    } catch (const std::exception& e) {
+      err = e.what();
+      ok = false;
+    }
+    lk.lock();
+    admit_ms += now_ms() - ta;
+    m.admitting = m.busy = false;
+    if (ok) {
       m.admitted = true;
-      used += m.footprint;
-    } catch (const Error& e) {
-      // cannot be made resident: fail its requests, drop it from the queue
+      ++admissions;
+    } else {
+      // cannot be made resident: fail its requests
+      used -= m.footprint;
       for (Request* q : m.pending) {
         q->state = 3;
-        q->error = e.what();
+        q->error = err;
         q->t_done = now_ms();
         ++failed;
       }
       m.pending.clear();
       release_model(m);
     }
-    admit_q.pop_front();
+    admit_job = 0;
+    cv.notify_all();
+    done_cv.notify_all();
   }
 }
 
@@ -178,6 +218,7 @@ void Server::retire() {
         } else {
           r->state = 2;
           lat.push_back(r->t_done - r->t_submit);
+          if (admit_job) lat_admitting.push_back(r->t_done - r->t_submit);
           ++completed;
         }
       }
@@ -206,6 +247,7 @@ bool Server::launch_one() {
     if ((int)pick.size() >= max_batch) break;
   }
   if (pick.empty()) return false;
+  const double th = now_ms();
   hipStream_t st = streams[si];
   const int k = (int)pick.size();
   std::vector<Compression*> cs(k);
@@ -271,7 +313,9 @@ bool Server::launch_one() {
   fl.ev = ev;
   stream_busy[si] = 1;
   flights.push_back(std::move(fl));
+  max_inflight = std::max<i64>(max_inflight, (i64)flights.size());
   ++batches;
+  host_ms += now_ms() - th;
   return true;
 }
 
@@ -284,7 +328,7 @@ void Server::loop() {
       retire();
       bool launched = false;
       while (launch_one()) launched = true;
-      if (stop && flights.empty()) {
+      if (stop && flights.empty() && !admit_job) {
         bool pending = false;
         for (auto& kv : models) pending |= kv.second->admitted && !kv.second->pending.empty();
         if (!pending) break;
@@ -356,6 +400,7 @@ extern "C" int gofmm_server_create(int64_t hbm_budget, int32_t streams, int32_t 
       s.stream_busy.push_back(0);
     }
     s.th = std::thread([&s] { s.loop(); });
+    s.admitter = std::thread([&s] { s.admit_loop(); });
     *out = h.release();
   });
 }
@@ -413,6 +458,7 @@ extern "C" int gofmm_server_submit(gofmm_server* h, int32_t model, int64_t r, co
   return sguard([&] {
     if (!h || !W || !U || !request) fail(GOFMM_EINVAL, "NULL argument");
     Server& s = h->s;
+    const double t_submit = now_ms();     // before waiting for the lock
     std::lock_guard<std::mutex> g(s.mu);
     auto it = s.models.find(model);
     if (it == s.models.end() || it->second->removing) fail(GOFMM_EINVAL, "unknown model");
@@ -427,7 +473,7 @@ extern "C" int gofmm_server_submit(gofmm_server* h, int32_t model, int64_t r, co
     q->ldw = ldw;
     q->U = U;
     q->ldu = ldu;
-    q->t_submit = now_ms();
+    q->t_submit = t_submit;
     m.pending.push_back(q.get());
     *request = q->id;
     s.reqs[q->id] = std::move(q);
@@ -506,6 +552,15 @@ extern "C" int gofmm_server_stats(gofmm_server* h, gofmm_server_stats_t* out) {
       out->mean_ms = sum / (double)v.size();
     }
     out->elapsed_ms = now_ms() - s.t0;
+    out->max_inflight = s.max_inflight;
+    out->admissions = s.admissions;
+    out->host_ms_mean = s.batches ? s.host_ms / (double)s.batches : 0.0;
+    out->admit_ms_mean = s.admissions ? s.admit_ms / (double)s.admissions : 0.0;
+    if (!s.lat_admitting.empty()) {
+      std::vector<double> v(s.lat_admitting);
+      std::sort(v.begin(), v.end());
+      out->p99_ms_admitting = v[std::min(v.size() - 1, (size_t)(0.99 * (double)(v.size() - 1) + 0.5))];
+    }
   });
 }
 
@@ -515,7 +570,10 @@ extern "C" int gofmm_server_reset_stats(gofmm_server* h) {
     Server& s = h->s;
     std::lock_guard<std::mutex> g(s.mu);
     s.lat.clear();
+    s.lat_admitting.clear();
     s.completed = s.failed = s.batches = s.columns = s.packed = 0;
+    s.max_inflight = s.admissions = 0;
+    s.host_ms = s.admit_ms = 0;
     s.t0 = now_ms();
   });
 }
@@ -529,6 +587,12 @@ extern "C" void gofmm_server_destroy(gofmm_server* h) {
     s.cv.notify_all();
   }
   if (s.th.joinable()) s.th.join();
+  {
+    std::lock_guard<std::mutex> g(s.mu);
+    s.stop_admit = true;
+    s.admit_cv.notify_all();
+  }
+  if (s.admitter.joinable()) s.admitter.join();
   (void)hipSetDevice(s.device);
   for (auto& kv : s.models) s.release_model(*kv.second);
   s.rings.clear();

@@ -170,3 +170,58 @@ def test_footprint_over_budget_rejected(env):
         assert e.value.code == -4
     finally:
         srv.close()
+
+
+def test_batches_overlap_and_admission_runs_beside_them(env):
+    """Continuous batching: with two streams, a second batch is enqueued while
+    the first is still on the device (the stats record two batches in flight
+    at once), and a model admitted while requests of the resident ones arrive
+    does not stall them: requests finish during its upload, which runs on the
+    admission thread.  Every result still equals its standalone evaluate."""
+    g, torch, comps, Ks = env
+    log("case overlap: two streams, one large admission during a stream of requests")
+    rng = np.random.default_rng(5)
+    n_big = 60000
+    pts = rng.random((n_big, 3))
+    big = g.Compression.compress(g.KernelSampler(pts, "gaussian", 0.3, 1e-2), leaf_size=256, max_rank=256,
+                                 tol=1e-7, kappa=16, budget=0.05, seed=9)
+    reqs = _requests(torch, comps, per_model=12, seed=7)
+    alone = [comps[i].evaluate(W) for i, W in reqs]
+    torch.cuda.synchronize()
+    alone = [a.cpu().numpy() for a in alone]
+    srv = g.Server(hbm_budget_bytes=32 << 30, streams=2, max_batch=2)
+    try:
+        ids = [srv.add(c, 64) for c in comps]
+        outs = [torch.full_like(W, float("nan")) for _, W in reqs]
+        torch.cuda.synchronize()
+        while srv.stats().models < len(comps):
+            time.sleep(0.01)
+        handles = []
+        half = len(reqs) // 2
+        for j, (i, W) in enumerate(reqs):
+            handles.append(srv.submit(ids[i], W, outs[j]))   # a burst: both streams get a batch
+            if j == half:
+                mb = srv.add(big, 128)          # its upload overlaps the requests below
+            if j >= half:
+                time.sleep(0.002)
+        for h in handles:
+            srv.wait(h, timeout_ms=60000)
+        while srv.stats().models < len(comps) + 1:
+            time.sleep(0.01)
+        st = srv.stats()
+        log(f"  batches {st.batches}, most in flight {st.max_inflight}, admissions {st.admissions}, "
+            f"host ms per batch {st.host_ms_mean:.3f}, admission ms {st.admit_ms_mean:.1f}, "
+            f"p99 while admitting {st.p99_ms_admitting:.2f} ms, p50 {st.p50_ms:.2f} p99 {st.p99_ms:.2f}")
+        assert st.failed == 0 and st.max_inflight >= 2
+        assert st.admissions == len(comps) + 1 and st.admit_ms_mean > 0
+        assert st.p99_ms_admitting > 0              # requests finished while the big model uploaded
+        for j in range(len(reqs)):
+            assert np.array_equal(outs[j].cpu().numpy(), alone[j]), j
+        W = cuda_rhs(big.n, 40, 2)[1]
+        U = torch.empty_like(W)
+        torch.cuda.synchronize()
+        srv.wait(srv.submit(mb, W, U), timeout_ms=60000)
+        srv.remove(mb)
+        assert np.array_equal(U.cpu().numpy(), big.evaluate(W).cpu().numpy())
+    finally:
+        srv.close()
