@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
-"""Throughput of K~W on one MI355X: the N=65536 clustered-Gaussian workload.
+"""Throughput of K~W on one MI355X: the N=262144 inverse-multiquadric workload at r=2048.
 
-Workload: 8 Gaussian clusters (sigma 0.1) in 6-D, Gaussian kernel with
-bandwidth 0.8 and diagonal shift 1e-2, leaf size 256, max rank 256,
-tau 1e-5, kappa 32, near budget 3%; r = 512 FP32 right-hand sides.
+Headline workload: 262144 uniform points in 4-D, inverse multiquadric kernel
+1/sqrt(1 + |x - y|^2 / 0.3^2) plus 1e-2 on the diagonal, leaf size 512, max
+rank 512, tau 1e-6, kappa 32, near budget 3%; r = 2048 FP32 right-hand sides
+(the largest workload that one GPU holds).  The same structure is also timed
+with BF16 P and coupling blocks (near blocks FP32) and with split-BF16
+storage, and the N=65536 clustered-Gaussian workload (r = 512) follows as a
+secondary block.
 
 A step is one whole K~W (every launch of N2S, S2S, S2N and L2L, the
 permutation folded in) with W and U resident in HBM.  The compression is
 built on the host first and is not timed.  The reported value is the
 dense-equivalent rate 2 N^2 r / t.  The roofline block covers the dominant
 launch: its Table 2 flops divided by its average duration, measured with HIP
-events around each launch on the evaluation stream during the timed steps.
-The CPU baseline times the FP64 oracle's tree walk of the whole K~W of the
-same compression (every row), repeated to about ten seconds.
+events around that launch on the evaluation stream during the timed steps,
+against the published peak and against ceilings measured on the same GPU
+(vendor GEMM, device copy).  The CPU baseline times the FP64 oracle's walk of
+the same compression restricted to 64 sampled rows (whole upward pass, then
+the far and near field of those rows), scaled to a whole K~W by Table 2
+flops, plus a one-thread figure on a smaller sample.
 """
 from __future__ import annotations
 
@@ -603,48 +610,15 @@ def form_copy(args):
     print(json.dumps({"form": "copy", "bytes": 4 << 28, "copies": 3}), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-geometric", action="store_true", help="skip the near-blocks-from-points form")
-    ap.add_argument("--rows", type=int, default=256, help="rows compared with the oracle and with exact K W")
-    ap.add_argument("--form", default="flat", choices=["flat", "batched", "serving", "large", "sweep", "copy"],
-                    help="flat: the N=65536 workload (default); batched: 48 compressions in one launch; "
-                         "serving: request loop with p50/p99; large: N=262144 in three precisions; "
-                         "sweep: accuracy and time over budget, rank and distance")
-    ap.add_argument("--instances", type=int, default=48, help="batched form: compressions")
-    ap.add_argument("--models", type=int, default=16, help="serving form: resident compressions")
-    ap.add_argument("--admissions", type=int, default=4, help="serving form: compressions admitted per Poisson run")
-    ap.add_argument("--requests", type=int, default=400)
-    ap.add_argument("--streams", type=int, default=2)
-    ap.add_argument("--hbm-gb", type=int, default=240)
-    ap.add_argument("--max-n", type=int, default=262144)
-    ap.add_argument("--r-list", type=int, nargs="+", default=[1024, 2048])
-    ap.add_argument("--precisions", nargs="+", default=["fp32", "bf16", "bf16x3"])
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark measures one GPU only: the evaluator has no "
-                                   "multi-GPU path (it would shard by subtrees, with one exchange of "
-                                   "skeleton weights and near-field W rows after the upward pass)",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-
+def form_flat(args):
+    """The N=65536 clustered-Gaussian workload alone (r = 512): FP32, split
+    BF16 and near blocks from the points, with the CPU baseline of the whole
+    K~W (the form the counter and trace summaries of the N=65536 kernels
+    were taken with)."""
     import numpy as np
     import torch
     import workloads
     import paper_1707_00164_amd as g
-
-    assert torch.cuda.is_available(), "no GPU"
-    g.lib()
-    if args.form != "flat":
-        {"batched": form_batched, "serving": form_serving, "large": form_large,
-         "sweep": form_sweep, "copy": form_copy}[args.form](args)
-        return
     w = workloads.clustered_gaussian()
     pts = workloads.points(w)
     S = g.KernelSampler(pts, w.kernel, w.h, w.shift)
@@ -755,6 +729,318 @@ def main():
             geo["eps2_vs_exact_KW"] = float(np.linalg.norm(Ug_rows - exact) / np.linalg.norm(exact))
         log(f"cpu oracle: {cb['value']} GFLOP/s on {cb['cores']} threads; parity {err:.2e}, eps2 {eps:.2e}")
     print(json.dumps(out), flush=True)
+
+
+
+# ---------------------------------------------------------------- headline form
+def measured_ceilings(torch):
+    """Ceilings measured on this GPU: vendor GEMM (torch.matmul, 8192^3) in
+    FP32 and BF16, and the bandwidth of a 4 GiB device-to-device copy."""
+    out = {}
+    n = 8192
+    for key, dt in (("fp32_gemm_tflops", torch.float32), ("bf16_gemm_tflops", torch.bfloat16)):
+        a = torch.randn(n, n, device="cuda", dtype=dt)
+        b = torch.randn(n, n, device="cuda", dtype=dt)
+        for _ in range(3):
+            c = torch.matmul(a, b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            c = torch.matmul(a, b)
+        e1.record()
+        torch.cuda.synchronize()
+        out[key] = round(2.0 * n ** 3 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e12, 1)
+        del a, b, c
+    x = torch.ones(1 << 30, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_gbs"] = round(2.0 * 4 * (1 << 30) * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
+def with_ceiling(rl, ceil, form):
+    """Adds the fraction of the measured ceiling of the form's arithmetic."""
+    if ceil:
+        base, products = FORM_PEAK[form if not (rl["kernel"] == "l2l" and rl.get("near_form")) else rl["near_form"]]
+        v = ceil["fp32_gemm_tflops"] if base == "f32" else ceil["bf16_gemm_tflops"] / products
+        rl["measured_ceiling"] = {"tflops": round(v, 1), "what": "torch.matmul 8192^3 on this GPU"
+                                  + ("" if products == 1 else f" / {products:g} products")}
+        rl["frac_vs_measured"] = round(rl["achieved"] / v, 4)
+    return rl
+
+
+def run_form(comp, W, U, args, torch, form, near_form=None, ceil=None, autotune=True):
+    """Autotune, then time `args.steps` evaluates after `args.warmup`: ms per
+    step (wall clock), per-step median (HIP events) and the roofline of the
+    dominant launch."""
+    r = W.shape[1]
+    comp.prepare(r)
+    if autotune and not args.no_autotune:
+        comp.autotune(W, U)
+    torch.cuda.synchronize()
+    sec, dom, dom_ms, share = time_steps(comp, W, U, args.steps, args.warmup, torch)
+    rl = roofline(comp, dom, dom_ms, share, r, form, near_form=near_form)
+    if near_form is not None and near_form != form:
+        rl["near_form"] = near_form
+    rl = with_ceiling(rl, ceil, form)
+    st = comp.stats()
+    n = st.n
+    return {"value": round(2.0 * n * n * r / sec / 1e9, 2), "unit": "GFLOP/s",
+            "ms_per_step": round(sec * 1e3, 4), "ms_per_step_median": round(time_steps.median_ms, 4),
+            "algorithmic_tflops": round(st.flops_per_rhs * r / sec / 1e12, 3),
+            "flops_per_step": st.flops_per_rhs * r, "roofline": rl}
+
+
+def sample_flops(c, rows, r):
+    """Table 2 flops of the oracle's walk restricted to `rows`: the whole
+    upward pass, then S2S, S2N and L2L on the leaves holding the rows and the
+    nodes above them."""
+    import numpy as np
+    from oracle import cfile
+    fl = cfile.first_leaf(c.depth)
+    pos_of = np.empty(c.n, dtype=np.int64)
+    pos_of[c.perm] = np.arange(c.n)
+    leaves = set((np.searchsorted(c.node_start[fl:], pos_of[rows], side="right") - 1).tolist())
+    want = set()
+    for b in leaves:
+        x = fl + b
+        while x > 0:
+            want.add(x)
+            x = (x - 1) // 2
+    f = 0.0
+    for h in range(1, c.nn):
+        s = c.rank(h)
+        ncol = int(c.node_size[h]) if h >= fl else c.rank(2 * h + 1) + c.rank(2 * h + 2)
+        f += 2.0 * s * ncol * r * (2 if h in want else 1)           # N2S, and S2N where wanted
+        if h in want:
+            f += sum(2.0 * s * c.rank(int(a)) * r for a in c.far[h])
+    for b in leaves:
+        f += sum(2.0 * int(c.node_size[fl + b]) * int(c.node_size[int(a)]) * r for a in c.near[b])
+    return f
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_rows(c, K, W64, rows, n, sample_desc):
+    """The FP64 oracle's walk of the same compression restricted to `rows`
+    (the whole upward pass, then S2S, S2N and L2L on the rows' leaves and the
+    nodes above them), timed once on the host's BLAS threads, then on one
+    thread over a smaller sample (8 rows, 256 right-hand sides).  The rate is
+    scaled to the metric's unit: the whole K~W's Table 2 flops over the
+    sample's, times the sample's time, is the time of a whole walk at that
+    rate; value = 2 N^2 r / that time.  Returns (baseline, oracle rows)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import evaluate
+    r = W64.shape[1]
+    threads = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
+    full = evaluate.algorithmic_flops(c, r)
+    t0 = time.perf_counter()
+    ref = evaluate.tree_walk(c, K, W64, rows)
+    t = time.perf_counter() - t0
+    fs = sample_flops(c, rows, r)
+    res = {"value": round(2.0 * n * n * r / (t * full / fs) / 1e9, 3), "unit": "GFLOP/s", "cores": int(threads),
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"FP64 tree walk of the same compression for {len(rows)} sampled rows at r={r} "
+                     f"({sample_desc}): the whole upward pass plus S2S, S2N and L2L on the rows' leaves and "
+                     f"the nodes above them, {fs:.3e} Table 2 flops of the whole K~W's {full:.3e}, "
+                     f"in {t:.2f} s; value = 2 N^2 r / (t * whole flops / sample flops)",
+           "seconds": round(t, 3), "algorithmic_gflops": round(fs / t / 1e9, 2)}
+    rows1, r1 = rows[:8], min(r, 256)
+    W1 = W64[:, :r1].copy()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        evaluate.tree_walk(c, K, W1, rows1)
+        t1 = time.perf_counter() - t0
+    fs1, full1 = sample_flops(c, rows1, r1), evaluate.algorithmic_flops(c, r1)
+    res["one_thread"] = {"value": round(2.0 * n * n * r1 / (t1 * full1 / fs1) / 1e9, 3), "cores": 1,
+                         "sample": f"{len(rows1)} rows at r={r1}: {fs1:.3e} of {full1:.3e} flops in {t1:.2f} s",
+                         "seconds": round(t1, 3), "algorithmic_gflops": round(fs1 / t1 / 1e9, 2)}
+    return res, ref
+
+
+def form_headline(args):
+    """The default line: the N=262144 inverse-multiquadric workload at r=2048
+    in FP32 (the headline), then the same structure with BF16 P and coupling
+    blocks (near FP32) and with split BF16 everywhere, then the N=65536
+    clustered Gaussian at r=512 (FP32 and split BF16) as a secondary block;
+    accuracy of every form on sampled rows against the FP64 oracle and the
+    exact K W; the CPU baseline on the oracle's row-sampled walk."""
+    import tempfile
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1707_00164_amd as g
+    from oracle import cfile, dense, kernels
+
+    ceil = measured_ceilings(torch)
+    log(f"measured ceilings: {ceil}")
+    w = workloads.large_imq(r=args.r)
+    pts = workloads.points(w)
+    S = g.KernelSampler(pts, w.kernel, w.h, w.shift)
+    t0 = time.perf_counter()
+    base = g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol, kappa=w.kappa,
+                                  budget=w.budget, seed=w.seed)
+    t_comp = time.perf_counter() - t0
+    st = base.stats()
+    log(f"compressed N={w.n} in {t_comp:.1f} s: depth {st.depth}, mean rank "
+        f"{st.rank_sum / max(1, st.n_nodes - 1):.1f}, near pairs {st.near_pairs}, far pairs {st.far_pairs}, "
+        f"{st.flops_per_rhs * w.r:.3e} flops/step, operator {st.operator_bytes / 1e9:.1f} GB")
+    fd, path = tempfile.mkstemp(suffix=".gofmm")
+    os.close(fd)
+    base.export(path)
+    rows = workloads.sample_rows(w.n, 64, w.seed)
+    W = torch.from_numpy(workloads.rhs(w.n, w.r, w.seed).astype(np.float32)).cuda()
+    U = torch.empty_like(W)
+    head = run_form(base, W, U, args, torch, "f32", ceil=ceil)
+    got = {"fp32": U.cpu().numpy()[rows].astype(np.float64)}
+    log(f"fp32: {head['ms_per_step']:.2f} ms/step, effective {head['value']:.1f} GFLOP/s; dominant "
+        f"{head['roofline']['kernel']} {head['roofline']['achieved']} TFLOP/s "
+        f"({100 * head['roofline']['frac']:.1f}% of {head['roofline']['peak']})")
+    base.free()
+    del base
+    torch.cuda.empty_cache()
+    forms = {}
+    for name, sp, sn, f, nf in (("bf16", g.BF16, g.FP32, "bf16", "f32"),
+                                ("bf16x3", g.BF16X3, g.BF16X3, "bf16x3", "bf16x3")):
+        if name not in args.precisions:
+            continue
+        cc = g.Compression.load(path, S, storage=sp, near_storage=sn)
+        res = run_form(cc, W, U, args, torch, f, near_form=nf, ceil=ceil)
+        res["storage"] = {"bf16": "P and coupling blocks BF16 (right-hand operands rounded to BF16), near "
+                                  "blocks FP32",
+                          "bf16x3": "split BF16 everywhere (x = hi + lo; 3 BF16 matrix-core products per step)"}[name]
+        res["speedup_vs_fp32"] = round(head["ms_per_step"] / res["ms_per_step"], 3)
+        got[name] = U.cpu().numpy()[rows].astype(np.float64)
+        forms[name] = res
+        log(f"{name}: {res['ms_per_step']:.2f} ms/step ({res['speedup_vs_fp32']:.2f}x fp32); dominant "
+            f"{res['roofline']['kernel']} {res['roofline']['achieved']} TFLOP/s")
+        cc.free()
+        del cc
+        torch.cuda.empty_cache()
+    W64 = W.cpu().numpy().astype(np.float64)
+    del W, U
+    torch.cuda.empty_cache()
+
+    out = {
+        "metric": METRIC, "value": head["value"], "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "ms_per_step_median": head["ms_per_step_median"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded uniform 4-D points; the paper's matrices are not available)",
+        "config": {"workload": f"imq4d_n262144_r{w.r}", "n": w.n, "r": w.r, "dim": w.dim, "kernel": w.kernel,
+                   "h": w.h, "shift": w.shift, "leaf_size": w.leaf_size, "max_rank": w.max_rank, "tol": w.tol,
+                   "kappa": w.kappa, "budget": w.budget, "storage": "fp32", "parallelism": "single GPU"},
+        "algorithmic_tflops": head["algorithmic_tflops"], "flops_per_step": head["flops_per_step"],
+        "compress_seconds": round(t_comp, 2), "roofline": head["roofline"],
+        "precision_forms": forms, "measured_ceilings": ceil,
+    }
+
+    if not args.no_secondary:
+        out["secondary"] = secondary_block(args, torch, ceil)
+
+    c = cfile.read(path)
+    os.unlink(path)
+    K = kernels.KernelMatrix(pts, w.kernel, w.h, w.shift)
+    if not args.no_cpu_baseline:
+        cb, ref = cpu_baseline_rows(c, K, W64, rows, w.n, f"N={w.n}, r={w.r}")
+        out["cpu_baseline"] = cb
+        log(f"cpu oracle: {cb['value']} GFLOP/s equivalent on {cb['cores']} threads "
+            f"({cb['algorithmic_gflops']} GFLOP/s algorithmic); one thread {cb['one_thread']['value']}")
+        exact = dense.kw(K, W64, rows)
+        acc = {"rows": len(rows)}
+        for name, v in got.items():
+            acc[name] = {"gpu_vs_oracle_same_compression": float(np.linalg.norm(v - ref) / np.linalg.norm(ref)),
+                         "eps2_vs_exact_KW": float(np.linalg.norm(v - exact) / np.linalg.norm(exact))}
+        out["accuracy"] = acc
+        log(f"accuracy on {len(rows)} rows: {acc}")
+    print(json.dumps(out), flush=True)
+
+
+def secondary_block(args, torch, ceil):
+    """The N=65536 clustered Gaussian at r=512 in FP32 and split BF16."""
+    import numpy as np
+    import workloads
+    import paper_1707_00164_amd as g
+    w = workloads.clustered_gaussian()
+    pts = workloads.points(w)
+    S = g.KernelSampler(pts, w.kernel, w.h, w.shift)
+    W = torch.from_numpy(workloads.rhs(w.n, w.r, w.seed).astype(np.float32)).cuda()
+    U = torch.empty_like(W)
+    res = {"workload": f"gauss6d_n65536_r{w.r}", "n": w.n, "r": w.r}
+    for name, prec, f in (("fp32", g.FP32, "f32"), ("bf16x3", g.BF16X3, "bf16x3")):
+        cc = g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol, kappa=w.kappa,
+                                    budget=w.budget, seed=w.seed, storage=prec, near_storage=prec)
+        res[name] = run_form(cc, W, U, args, torch, f, ceil=ceil)
+        log(f"secondary {name}: {res[name]['ms_per_step']:.3f} ms/step, dominant "
+            f"{res[name]['roofline']['kernel']} {res[name]['roofline']['achieved']} TFLOP/s")
+        cc.free()
+    res["bf16x3"]["speedup_vs_fp32"] = round(res["fp32"]["ms_per_step"] / res["bf16x3"]["ms_per_step"], 3)
+    del W, U
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-geometric", action="store_true", help="flat form: skip the near-blocks-from-points form")
+    ap.add_argument("--no-secondary", action="store_true", help="headline form: skip the N=65536 block")
+    ap.add_argument("--r", type=int, default=2048, help="headline form: right-hand sides")
+    ap.add_argument("--rows", type=int, default=256, help="rows compared with the oracle and with exact K W")
+    ap.add_argument("--form", default="headline",
+                    choices=["headline", "flat", "batched", "serving", "large", "sweep", "copy"],
+                    help="headline: N=262144 at r=2048 in FP32 with BF16 and split-BF16 forms and the "
+                         "N=65536 workload as a secondary block (default); flat: the N=65536 workload alone; "
+                         "batched: 48 compressions in one launch; serving: request loop with p50/p99; "
+                         "large: N=262144 over several r; sweep: accuracy and time over budget, rank and "
+                         "distance")
+    ap.add_argument("--instances", type=int, default=48, help="batched form: compressions")
+    ap.add_argument("--models", type=int, default=16, help="serving form: resident compressions")
+    ap.add_argument("--admissions", type=int, default=4, help="serving form: compressions admitted per Poisson run")
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--streams", type=int, default=2)
+    ap.add_argument("--hbm-gb", type=int, default=240)
+    ap.add_argument("--max-n", type=int, default=262144)
+    ap.add_argument("--r-list", type=int, nargs="+", default=[1024, 2048])
+    ap.add_argument("--precisions", nargs="+", default=["fp32", "bf16", "bf16x3"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark measures one GPU only: the evaluator has no "
+                                   "multi-GPU path (it would shard by subtrees, with one exchange of "
+                                   "skeleton weights and near-field W rows after the upward pass)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1707_00164_amd as g
+
+    assert torch.cuda.is_available(), "no GPU"
+    g.lib()
+    {"headline": form_headline, "flat": form_flat, "batched": form_batched, "serving": form_serving,
+     "large": form_large, "sweep": form_sweep, "copy": form_copy}[args.form](args)
 
 
 if __name__ == "__main__":

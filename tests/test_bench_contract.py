@@ -34,3 +34,27 @@ def test_counter_figures_follow_the_sources():
     else:
         assert rl["traffic"] is None
     assert rl["frac"] == round(rl["achieved"] / 157.3, 4)
+
+
+def test_sampled_walk_flops():
+    """The CPU baseline's flop count of a row-restricted oracle walk equals
+    the whole K~W's Table 2 count when every row is asked for, and counts the
+    upward pass once and nothing else when no row is."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads
+    from oracle import compress, evaluate, kernels
+    rng = np.random.default_rng(3)
+    n = 700
+    K = kernels.KernelMatrix(rng.random((n, 3)), "gaussian", 0.3, 1e-3)
+    c = compress.compress(K, n, leaf_size=64, max_rank=24, tol=1e-6, kappa=8, budget=0.1, seed=2)
+    assert bench.sample_flops(c, np.arange(n), 5) == evaluate.algorithmic_flops(c, 5)
+    up = 0.0
+    for h in range(1, c.nn):
+        fl = (1 << c.depth) - 1
+        ncol = int(c.node_size[h]) if h >= fl else c.rank(2 * h + 1) + c.rank(2 * h + 2)
+        up += 2.0 * c.rank(h) * ncol * 5
+    assert bench.sample_flops(c, np.zeros(0, dtype=np.int64), 5) == up
+    rows = workloads.sample_rows(n, 10, 1)
+    assert up < bench.sample_flops(c, rows, 5) < evaluate.algorithmic_flops(c, 5)
