@@ -84,9 +84,11 @@ def time_steps(comp, W, U, steps, warmup, torch):
 FORM_PEAK = {"f32": ("f32", 1.0), "bf16": ("bf16", 1.0), "bf16x3": ("bf16", 3.0)}
 
 
-def roofline(comp, dom, dom_ms, share, r, form, near_form=None):
+def roofline(comp, dom, dom_ms, share, r, form, near_form=None, workload=None):
     """Roofline of the dominant launch; `near_form` is the precision form of
-    the near-field launch (l2l) when it differs from the rest."""
+    the near-field launch (l2l) when it differs from the rest.  Counter
+    figures (HBM traffic, matrix-core busy) come from profiles/ for this
+    launch, form and workload, if they were taken on the current sources."""
     name, fl, byts = comp.launches()[dom]
     if name == "l2l" and near_form is not None:
         form = near_form
@@ -94,13 +96,16 @@ def roofline(comp, dom, dom_ms, share, r, form, near_form=None):
     achieved = fl * r / avg_s / 1e12
     base, products = FORM_PEAK[form]
     peak = round(PEAK_TFLOPS[base] / products, 1)
+    def match(e):
+        return (e.get("launch") == name and e.get("form") == form and e.get("fingerprint") == _fingerprint()
+                and (workload is None or e.get("workload") == workload))
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
         try:
-            t = json.load(open(tfile))
-            if t.get("launch") == name and t.get("form", "f32") == form and t.get("fingerprint") == _fingerprint():
-                traffic = t.get("bytes_per_launch")
+            for e in json.load(open(tfile)):
+                if match(e):
+                    traffic = e.get("bytes_per_launch")
         except Exception:
             traffic = None
     # matrix-core busy cycles from the counters (SQ_VALU_MFMA_BUSY_CYCLES over
@@ -110,7 +115,7 @@ def roofline(comp, dom, dom_ms, share, r, form, near_form=None):
     if os.path.exists(mfile):
         try:
             for e in json.load(open(mfile)):
-                if e.get("launch") == name and e.get("form") == form and e.get("fingerprint") == _fingerprint():
+                if match(e):
                     mfma = {"mfma_busy_frac": round(e["mfma_busy_frac"], 4), "clock_ghz": round(e["clock_ghz"], 3),
                             "counted_tflops": round(e["counted_tflops"], 1)}
         except Exception:
@@ -126,10 +131,15 @@ def roofline(comp, dom, dom_ms, share, r, form, near_form=None):
 
 
 def _fingerprint():
+    """Hash of the sources that decide what the evaluation kernels read and
+    write: the kernel templates and their instantiations, the operator
+    packing, and the launch and work-item code."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1707_00164_amd", "csrc"))):
-        h.update(open(os.path.join(ROOT, "paper_1707_00164_amd", "csrc", f), "rb").read())
+    src = os.path.join(ROOT, "paper_1707_00164_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f == "kernels.hpp" or f.startswith("k_") or f in ("eval.hip", "pack.cpp"):
+            h.update(open(os.path.join(src, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -640,7 +650,7 @@ def form_flat(args):
     torch.cuda.synchronize()
     sec, dom, dom_ms, share = time_steps(comp, W, U, args.steps, args.warmup, torch)
     value = 2.0 * w.n * w.n * w.r / sec / 1e9
-    rl = roofline(comp, dom, dom_ms, share, w.r, "f32")
+    rl = roofline(comp, dom, dom_ms, share, w.r, "f32", workload=f"gauss6d_n65536_r{w.r}")
     alg_tflops = st.flops_per_rhs * w.r / sec / 1e12
     log(f"fp32: {sec * 1e3:.3f} ms/step, effective {value:.1f} GFLOP/s, algorithmic "
         f"{alg_tflops:.2f} TFLOP/s; dominant {rl['kernel']} {rl['achieved']} TFLOP/s "
@@ -677,7 +687,7 @@ def form_flat(args):
         if not args.no_autotune:
             comp3.autotune(W, U3)
         sec3, dom3, dom3_ms, share3 = time_steps(comp3, W, U3, args.steps, args.warmup, torch)
-        rl3 = roofline(comp3, dom3, dom3_ms, share3, w.r, "bf16x3")
+        rl3 = roofline(comp3, dom3, dom3_ms, share3, w.r, "bf16x3", workload=f"gauss6d_n65536_r{w.r}")
         mixed = {"storage": "bf16x3 (split BF16, 3 BF16 matrix-core products per step)",
                  "value": round(2.0 * w.n * w.n * w.r / sec3 / 1e9, 2), "unit": "GFLOP/s",
                  "ms_per_step": round(sec3 * 1e3, 4), "ms_per_step_median": round(time_steps.median_ms, 4),
@@ -779,7 +789,7 @@ def with_ceiling(rl, ceil, form):
     return rl
 
 
-def run_form(comp, W, U, args, torch, form, near_form=None, ceil=None, autotune=True):
+def run_form(comp, W, U, args, torch, form, near_form=None, ceil=None, autotune=True, workload=None):
     """Autotune, then time `args.steps` evaluates after `args.warmup`: ms per
     step (wall clock), per-step median (HIP events) and the roofline of the
     dominant launch."""
@@ -789,7 +799,7 @@ def run_form(comp, W, U, args, torch, form, near_form=None, ceil=None, autotune=
         comp.autotune(W, U)
     torch.cuda.synchronize()
     sec, dom, dom_ms, share = time_steps(comp, W, U, args.steps, args.warmup, torch)
-    rl = roofline(comp, dom, dom_ms, share, r, form, near_form=near_form)
+    rl = roofline(comp, dom, dom_ms, share, r, form, near_form=near_form, workload=workload)
     if near_form is not None and near_form != form:
         rl["near_form"] = near_form
     rl = with_ceiling(rl, ceil, form)
@@ -909,7 +919,8 @@ def form_headline(args):
     rows = workloads.sample_rows(w.n, 64, w.seed)
     W = torch.from_numpy(workloads.rhs(w.n, w.r, w.seed).astype(np.float32)).cuda()
     U = torch.empty_like(W)
-    head = run_form(base, W, U, args, torch, "f32", ceil=ceil)
+    wl = f"imq4d_n262144_r{w.r}"
+    head = run_form(base, W, U, args, torch, "f32", ceil=ceil, workload=wl)
     got = {"fp32": U.cpu().numpy()[rows].astype(np.float64)}
     log(f"fp32: {head['ms_per_step']:.2f} ms/step, effective {head['value']:.1f} GFLOP/s; dominant "
         f"{head['roofline']['kernel']} {head['roofline']['achieved']} TFLOP/s "
@@ -923,7 +934,7 @@ def form_headline(args):
         if name not in args.precisions:
             continue
         cc = g.Compression.load(path, S, storage=sp, near_storage=sn)
-        res = run_form(cc, W, U, args, torch, f, near_form=nf, ceil=ceil)
+        res = run_form(cc, W, U, args, torch, f, near_form=nf, ceil=ceil, workload=wl)
         res["storage"] = {"bf16": "P and coupling blocks BF16 (right-hand operands rounded to BF16), near "
                                   "blocks FP32",
                           "bf16x3": "split BF16 everywhere (x = hi + lo; 3 BF16 matrix-core products per step)"}[name]
@@ -945,7 +956,7 @@ def form_headline(args):
         "ms_per_step_median": head["ms_per_step_median"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded uniform 4-D points; the paper's matrices are not available)",
-        "config": {"workload": f"imq4d_n262144_r{w.r}", "n": w.n, "r": w.r, "dim": w.dim, "kernel": w.kernel,
+        "config": {"workload": wl, "n": w.n, "r": w.r, "dim": w.dim, "kernel": w.kernel,
                    "h": w.h, "shift": w.shift, "leaf_size": w.leaf_size, "max_rank": w.max_rank, "tol": w.tol,
                    "kappa": w.kappa, "budget": w.budget, "storage": "fp32", "parallelism": "single GPU"},
         "algorithmic_tflops": head["algorithmic_tflops"], "flops_per_step": head["flops_per_step"],
@@ -988,7 +999,7 @@ def secondary_block(args, torch, ceil):
     for name, prec, f in (("fp32", g.FP32, "f32"), ("bf16x3", g.BF16X3, "bf16x3")):
         cc = g.Compression.compress(S, leaf_size=w.leaf_size, max_rank=w.max_rank, tol=w.tol, kappa=w.kappa,
                                     budget=w.budget, seed=w.seed, storage=prec, near_storage=prec)
-        res[name] = run_form(cc, W, U, args, torch, f, ceil=ceil)
+        res[name] = run_form(cc, W, U, args, torch, f, ceil=ceil, workload=res["workload"])
         log(f"secondary {name}: {res[name]['ms_per_step']:.3f} ms/step, dominant "
             f"{res[name]['roofline']['kernel']} {res[name]['roofline']['achieved']} TFLOP/s")
         cc.free()

@@ -26,11 +26,13 @@ def test_counter_figures_follow_the_sources():
         def launches(self):
             return [("leaf", 1.0e9, 1 << 20)]
 
-    rl = bench.roofline(Launches(), 0, 1.0, {"leaf": 1.0}, 512, "f32")
+    rl = bench.roofline(Launches(), 0, 1.0, {"leaf": 1.0}, 512, "f32", workload="gauss6d_n65536_r512")
     with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
-        traffic = json.load(f)
-    if traffic["fingerprint"] == bench._fingerprint():
-        assert rl["traffic"] == traffic["bytes_per_launch"]
+        entries = [e for e in json.load(f) if e["launch"] == "leaf" and e["form"] == "f32"
+                   and e["workload"] == "gauss6d_n65536_r512"]
+    current = [e for e in entries if e["fingerprint"] == bench._fingerprint()]
+    if current:
+        assert rl["traffic"] == current[-1]["bytes_per_launch"]
     else:
         assert rl["traffic"] is None
     assert rl["frac"] == round(rl["achieved"] / 157.3, 4)
