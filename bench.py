@@ -118,6 +118,9 @@ def roofline(comp, dom, dom_ms, share, r, form, near_form=None, workload=None):
                 if match(e):
                     mfma = {"mfma_busy_frac": round(e["mfma_busy_frac"], 4), "clock_ghz": round(e["clock_ghz"], 3),
                             "counted_tflops": round(e["counted_tflops"], 1)}
+                    if "padding_frac" in e:
+                        mfma["padding_frac"] = round(e["padding_frac"], 4)
+                        mfma["lds_bank_conflict_frac"] = round(e["lds_bank_conflict_frac"], 4)
         except Exception:
             mfma = None
     out = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
