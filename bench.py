@@ -213,6 +213,8 @@ def form_batched(args):
     import workloads
     import paper_1707_00164_amd as g
     insts = workloads.batched_instances(args.instances)
+    ceil = measured_ceilings(torch)
+    log(f"measured ceilings: {ceil}")
     comps, Ws, Us, Ss = [], [], [], []
     t0 = time.perf_counter()
     for w in insts:
@@ -259,6 +261,10 @@ def form_batched(args):
         base, products = FORM_PEAK["f32" if name == "fp32" else name]
         peak = PEAK_TFLOPS[base] / products
         t_roof = max(flops / (peak * 1e12), (opb + io) / (HBM_GBS * 1e9))
+        # the same bound with the ceilings measured on this GPU (vendor GEMM of
+        # the form's arithmetic, device copy bandwidth)
+        peak_m = ceil["fp32_gemm_tflops"] if base == "f32" else ceil["bf16_gemm_tflops"] / products
+        t_roof_m = max(flops / (peak_m * 1e12), (opb + io) / (ceil["copy_gbs"] * 1e9))
         # per phase (each launch of each instance on its own roof, then summed):
         # the bound when phases did not overlap
         t_phase = 0.0
@@ -282,11 +288,15 @@ def form_batched(args):
             "roofline": {"bound": "time", "t_roof_ms": round(t_roof * 1e3, 4), "frac": round(t_roof / sec, 4),
                          "flops": flops, "bytes": opb + io, "peak_tflops": round(peak, 1),
                          "t_roof_per_phase_ms": round(t_phase * 1e3, 4), "frac_per_phase": round(t_phase / sec, 4),
+                         "t_roof_measured_ms": round(t_roof_m * 1e3, 4), "frac_vs_measured": round(t_roof_m / sec, 4),
+                         "measured_ceilings": ceil,
                          "note": "frac: whole job, max(flops / matrix-core peak of the form, operator + W + U "
                                  "bytes / 8 TB/s); frac_per_phase: the same bound per launch of each instance, "
-                                 "summed"}}
+                                 "summed; frac_vs_measured: the whole-job bound with the vendor GEMM and "
+                                 "device-copy ceilings measured in this run"}}
         log(f"batched {name}: {sec * 1e3:.2f} ms/step ({seq / sec:.2f}x sequential), "
-            f"{flops / sec / 1e12:.1f} TFLOP/s algorithmic, roofline frac {t_roof / sec:.3f}, eps2 {err:.2e}")
+            f"{flops / sec / 1e12:.1f} TFLOP/s algorithmic, roofline frac {t_roof / sec:.3f} "
+            f"({t_roof_m / sec:.3f} of the measured ceilings), eps2 {err:.2e}")
         for c in cs:                                      # host and device copies of this form
             c.free()
         torch.cuda.empty_cache()
@@ -393,6 +403,8 @@ def form_serving(args):
     import torch
     import workloads
     import paper_1707_00164_amd as g
+    ceil = measured_ceilings(torch)
+    log(f"measured ceilings: {ceil}")
     ws = [w for w in workloads.serving_instances(args.models) if w.n <= args.max_n]
     n_res = len(ws)
     allw = ws + (workloads.serving_admissions(args.admissions) if args.admissions > 0 else [])
@@ -508,14 +520,21 @@ def form_serving(args):
             # lower bound on the time of this request mix: every flop at the
             # form's matrix-core peak, or every model used read once plus W and U
             t_roof = max(F / (peak * 1e12), (sum(op_bytes[i] for i in used) + io) / (HBM_GBS * 1e9))
+            peak_m = ceil["fp32_gemm_tflops"] if base_peak == "f32" else ceil["bf16_gemm_tflops"] / products
+            t_roof_m = max(F / (peak_m * 1e12), (sum(op_bytes[i] for i in used) + io) / (ceil["copy_gbs"] * 1e9))
             out = {"requests": n_req, "qps_offered": round(qps, 1) if qps else None,
                    "throughput_rps": round(st.completed / sec, 1),
                    "columns_per_s": round(st.columns / sec, 1),
                    "p50_ms": round(st.p50_ms, 3), "p99_ms": round(st.p99_ms, 3), "mean_ms": round(st.mean_ms, 3),
-                   "batches": st.batches, "failed": st.failed,
+                   "batches": st.batches, "failed": st.failed, "most_batches_in_flight": st.max_inflight,
+                   "host_ms_per_batch": round(st.host_ms_mean, 3), "admissions_done": st.admissions,
+                   "admission_ms_mean": round(st.admit_ms_mean, 1),
+                   "p99_ms_while_admitting": round(st.p99_ms_admitting, 3),
                    "algorithmic_tflops": round(F / sec / 1e12, 3),
                    "roofline": {"bound": "time", "t_roof_ms": round(t_roof * 1e3, 3),
-                                "frac": round(t_roof / sec, 4), "peak_tflops": round(peak, 1)}}
+                                "frac": round(t_roof / sec, 4), "peak_tflops": round(peak, 1),
+                                "t_roof_measured_ms": round(t_roof_m * 1e3, 3),
+                                "frac_vs_measured": round(t_roof_m / sec, 4)}}
             if admissions:
                 out["admissions"] = admissions
                 out["first_request_ms_of_admitted"] = first_ms
