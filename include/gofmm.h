@@ -99,6 +99,16 @@ typedef struct {
                                host, bit for bit.  Needs kappa <= 64 and
                                n < 2^31; the host still samples every block.
                                0 (default): everything on the host */
+  int32_t device_id;        /* 1: the interpolative decompositions of each tree
+                               level run on the current HIP device, all nodes of
+                               the level together (Alg. Skeletonize: pivoted QR
+                               in FP64 stopped at the adaptive rank, then
+                               R11^{-1} R12), with the host's steps and
+                               rounding: the same skeletons and P bit for bit.
+                               The host still samples every block.  Needs at
+                               most 8192 sampled rows per node (twice its
+                               columns: the leaf size at a leaf, at most 2 s_max
+                               above it), else GOFMM_ELIMIT.  0 (default): host */
 } gofmm_params;
 
 /* Summary of a built compression (for flop/byte accounting and reports). */

@@ -63,6 +63,7 @@ static void check_params(const gofmm_params* p) {
   if (!(p->ann_target_recall >= 0.0 && p->ann_target_recall <= 1.0)) fail(GOFMM_EINVAL, "ann_target_recall in [0,1]");
   if (p->device_knn != 0 && p->device_knn != 1) fail(GOFMM_EINVAL, "device_knn must be 0 or 1");
   if (p->device_knn && p->kappa > 64) fail(GOFMM_EINVAL, "device_knn keeps at most 64 neighbours");
+  if (p->device_id != 0 && p->device_id != 1) fail(GOFMM_EINVAL, "device_id must be 0 or 1");
 }
 
 extern "C" void gofmm_default_params(gofmm_params* p) {
@@ -82,6 +83,7 @@ extern "C" void gofmm_default_params(gofmm_params* p) {
   p->ann_target_recall = 0.8;
   p->exact_knn = 0;
   p->device_knn = 0;
+  p->device_id = 0;
 }
 
 extern "C" int gofmm_compress(int64_t n, gofmm_sampler sampler, void* user, const gofmm_params* params,

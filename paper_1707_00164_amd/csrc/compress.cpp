@@ -525,18 +525,21 @@ void build_compression(Compression& c, const Sampler& K, const gofmm_params& p) 
   c.proj.assign(nn, {});
   std::vector<i64> pos_of(n);
   for (i64 k = 0; k < n; ++k) pos_of[c.perm[k]] = k;
-  for (int lev = D; lev >= 1; --lev) {
-    const i64 h0 = (i64(1) << lev) - 1, cnt = i64(1) << lev;
-    parallel_for(cnt, threads, [&](i64 t) {
-      const i64 h = h0 + t;
+  // columns of node h (its indices at a leaf, the children's skeletons above)
+  // and its sampled rows I': neighbours outside the node by votes, then
+  // uniform draws from the complement (reading R10)
+  auto node_cols = [&](i64 h) {
+    const i64 st = c.node_start[h], sz = c.node_size[h];
+    std::vector<i64> cols;
+    if (h >= fl) cols.assign(c.perm.begin() + st, c.perm.begin() + st + sz);
+    else {
+      cols = c.skel[2 * h + 1];
+      cols.insert(cols.end(), c.skel[2 * h + 2].begin(), c.skel[2 * h + 2].end());
+    }
+    return cols;
+  };
+  auto node_rows = [&](i64 h, i64 ncols) {
       const i64 st = c.node_start[h], sz = c.node_size[h];
-      std::vector<i64> cols;
-      if (h >= fl) cols.assign(c.perm.begin() + st, c.perm.begin() + st + sz);
-      else {
-        cols = c.skel[2 * h + 1];
-        cols.insert(cols.end(), c.skel[2 * h + 2].begin(), c.skel[2 * h + 2].end());
-      }
-      const i64 ncols = (i64)cols.size();
       const i64 ns = std::min(n - sz, 2 * ncols);
       // neighbours outside the node, by votes (ties by index), at most half of the rows
       std::vector<i64> flat;
@@ -582,6 +585,50 @@ void build_compression(Compression& c, const Sampler& K, const gofmm_params& p) 
         std::sort(extra.begin(), extra.end());
         rows.insert(rows.end(), extra.begin(), extra.end());
       }
+      return rows;
+  };
+  for (int lev = D; lev >= 1; --lev) {
+    const i64 h0 = (i64(1) << lev) - 1, cnt = i64(1) << lev;
+    if (p.device_id) {
+      // every node of the level in one batch on the device: sample the
+      // blocks row-major (K is symmetric, so the sampler's column-major
+      // K(cols, I') is K(I', cols) row-major), then factor them together
+      std::vector<std::vector<i64>> cl(cnt), rw(cnt);
+      parallel_for(cnt, threads, [&](i64 t) {
+        cl[t] = node_cols(h0 + t);
+        rw[t] = node_rows(h0 + t, (i64)cl[t].size());
+      });
+      std::vector<IdJob> jobs(cnt);
+      i64 tot = 0;
+      for (i64 t = 0; t < cnt; ++t) {
+        jobs[t].a_off = tot;
+        jobs[t].nrow = (i64)rw[t].size();
+        jobs[t].ncol = (i64)cl[t].size();
+        tot += jobs[t].nrow * jobs[t].ncol;
+      }
+      std::vector<double> blocks((size_t)tot);
+      parallel_for(cnt, threads, [&](i64 t) {
+        double* A = &blocks[jobs[t].a_off];
+        K(jobs[t].ncol, cl[t].data(), jobs[t].nrow, rw[t].data(), A, jobs[t].ncol);
+        for (i64 q = 0; q < jobs[t].nrow * jobs[t].ncol; ++q)
+          if (!std::isfinite(A[q])) fail(GOFMM_ENOTSPD, "sampler returned a non-finite entry");
+      });
+      id_device_batch(jobs, blocks, c.tol, (int)c.max_rank);
+      for (i64 t = 0; t < cnt; ++t) {
+        const i64 h = h0 + t;
+        std::vector<i64> sk(jobs[t].rank);
+        for (int a = 0; a < jobs[t].rank; ++a) sk[a] = cl[t][jobs[t].piv[a]];
+        c.skel[h] = std::move(sk);
+        c.samp[h] = std::move(rw[t]);
+        c.proj[h] = std::move(jobs[t].P);
+      }
+      continue;
+    }
+    parallel_for(cnt, threads, [&](i64 t) {
+      const i64 h = h0 + t;
+      std::vector<i64> cols = node_cols(h);
+      const i64 ncols = (i64)cols.size();
+      std::vector<i64> rows = node_rows(h, ncols);
       std::vector<double> A((size_t)rows.size() * ncols);     // column-major
       K((i64)rows.size(), rows.data(), ncols, cols.data(), A.data(), (i64)rows.size());
       for (double x : A)

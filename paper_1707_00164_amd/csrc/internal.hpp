@@ -211,6 +211,18 @@ void knn_device_merge(KnnDevice* k, const std::vector<KnnTask>& tasks, const std
 void knn_device_read(KnnDevice* k, i64* knn);       // n x kappa, -1 for an empty entry
 void knn_device_free(KnnDevice* k);
 
+// Interpolative decompositions of a batch of sampled blocks on the device
+// (idqr.hip), with the steps and rounding of interp_decomp: each job's block
+// is row-major (nrow x ncol) at blocks[a_off]; fills rank, piv (ncol entries,
+// the first rank are the skeleton columns) and P (rank x ncol, row-major).
+struct IdJob {
+  i64 a_off = 0, nrow = 0, ncol = 0;
+  int rank = 0;
+  std::vector<int> piv;
+  std::vector<double> P;
+};
+void id_device_batch(std::vector<IdJob>& jobs, const std::vector<double>& blocks, double tol, int smax);
+
 // BF16 round-to-nearest-even of a double (through its nearest float).
 uint16_t to_bf16(double x);
 double from_bf16(uint16_t h);

@@ -31,7 +31,8 @@ class Params(C.Structure):
                 ("kappa", C.c_int32), ("budget", C.c_double), ("distance", C.c_int32),
                 ("storage", C.c_int32), ("near_storage", C.c_int32), ("seed", C.c_uint64),
                 ("threads", C.c_int32), ("ann_max_iters", C.c_int32),
-                ("ann_target_recall", C.c_double), ("exact_knn", C.c_int32), ("device_knn", C.c_int32)]
+                ("ann_target_recall", C.c_double), ("exact_knn", C.c_int32), ("device_knn", C.c_int32),
+                ("device_id", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -244,9 +244,15 @@ def test_error_codes(g):
         has_gpu = torch.cuda.is_available()
     except ImportError:
         has_gpu = False
+    with pytest.raises(g.GofmmError) as e:
+        g.Compression.compress(S, leaf_size=8, device_id=2)
+    assert e.value.code == -1
     if not has_gpu:
         with pytest.raises(g.GofmmError) as e:
             g.Compression.compress(S, leaf_size=8, device_knn=1)
+        assert e.value.code == -5
+        with pytest.raises(g.GofmmError) as e:
+            g.Compression.compress(S, leaf_size=8, device_id=1)
         assert e.value.code == -5
     # the allocation-free evaluate needs the compression on the device first
     assert L.gofmm_evaluate_noalloc(comp.h, 4, 4096, 4, 1 << 20, 4, None) == -1
