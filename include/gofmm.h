@@ -203,8 +203,9 @@ int gofmm_prepare(gofmm_compression* c, int64_t r_max);
  * tiles they read, through counters that only grow).  r == 0 is a no-op;
  * r > r_max of a previous prepare grows the workspace synchronously.
  * Errors: GOFMM_EINVAL (NULL c, W or U, r < 0, ldw or ldu < r, W and U
- * overlapping, a compression prepared on another device), GOFMM_ENOMEM (the
- * workspace), GOFMM_EHIP (a launch or copy failed).
+ * overlapping, a compression prepared on another device), GOFMM_ELIMIT (ldw
+ * above 2^32 - 1), GOFMM_ENOMEM (the workspace), GOFMM_EHIP (a launch or copy
+ * failed).
  */
 int gofmm_evaluate(gofmm_compression* c, int64_t r,
                    const float* W, int64_t ldw, float* U, int64_t ldu,

@@ -170,6 +170,7 @@ static void check_eval(const gofmm_compression* c, int64_t r, const float* W, in
   if (r == 0) return;
   if (!W || !U) fail(GOFMM_EINVAL, "NULL W or U");
   if (ldw < r || ldu < r) fail(GOFMM_EINVAL, "leading dimension smaller than r");
+  if (ldw > (int64_t)UINT32_MAX) fail(GOFMM_ELIMIT, "leading dimension of W above 2^32 - 1");
   const char* w0 = (const char*)W;
   const char* w1 = w0 + ((c->c.n - 1) * ldw + r) * 4;
   const char* u0 = (const char*)U;

@@ -216,16 +216,28 @@ void device_prepare(Compression& c, i64 r_max) {
 
 constexpr int kXcds = 8;   // MI355X: blocks are dealt to the 8 XCDs round-robin by id
 
-// Work items of launch li for tile configuration cfg and ntn column tiles:
-// the (task, row tile) groups sorted by k (longest first) are assigned to the
-// least-loaded XCD; each group's ntn column tiles stay on that XCD (they
-// share the A rows), and block id b runs item b % 8's queue entry b / 8.
+// Work items of launch li for tile configuration cfg and ntn column tiles;
+// block id b runs XCD b % 8's queue entry b / 8.  FP32 launches: the (task,
+// row tile) groups sorted by k (longest first) are assigned to the
+// least-loaded XCD, and each group's ntn column tiles stay on that XCD (they
+// share the A rows in its L2).  BF16 and split-BF16 launches, which stream
+// their operands two to three times as fast: whole tasks are assigned that
+// way, column tile by column tile with the row tiles of each column tile side
+// by side, so that the tiles running together on one XCD share both the A
+// rows and the gathered B rows, and both reach its L2 about once per task.
 static std::vector<int2> build_items(const HostPlan& pl, const LaunchDesc& l, int bm, int ntn) {
-  struct G { i32 task, mt; i64 cost; };
+  const bool together = l.prec != PREC_F32;
+  struct G { i32 task, mt, nmt; i64 cost; };
   std::vector<G> groups;
-  for (i32 k = l.t_begin; k < l.t_end; ++k)
-    for (int mt = 0; mt * bm < pl.tasks[k].m; ++mt)
-      groups.push_back({k, mt, (i64)std::max(pl.tasks[k].lda, 32)});
+  for (i32 k = l.t_begin; k < l.t_end; ++k) {
+    const int nmt = (int)((pl.tasks[k].m + bm - 1) / bm);
+    const i64 kc = (i64)std::max(pl.tasks[k].lda, 32);
+    if (nmt == 0) continue;
+    if (together)
+      groups.push_back({k, 0, nmt, kc * nmt});
+    else
+      for (int mt = 0; mt * bm < pl.tasks[k].m; ++mt) groups.push_back({k, mt, 1, kc});
+  }
   std::stable_sort(groups.begin(), groups.end(), [](const G& x, const G& y) { return x.cost > y.cost; });
   std::vector<std::vector<int2>> q(kXcds);
   std::vector<i64> load(kXcds, 0);
@@ -234,7 +246,8 @@ static std::vector<int2> build_items(const HostPlan& pl, const LaunchDesc& l, in
     for (int x = 1; x < kXcds; ++x)
       if (load[x] < load[best]) best = x;
     load[best] += g.cost * ntn;
-    for (int nt = 0; nt < ntn; ++nt) q[best].push_back(make_int2(g.task, (g.mt << 16) | nt));
+    for (int nt = 0; nt < ntn; ++nt)
+      for (int mt = g.mt; mt < g.mt + g.nmt; ++mt) q[best].push_back(make_int2(g.task, (mt << 16) | nt));
   }
   size_t len = 0;
   for (auto& v : q) len = std::max(len, v.size());
@@ -453,6 +466,13 @@ struct EvalArgs {
 
 // Kernel arguments of launch li; `fixed_items` and `fixed_ws` replace the
 // library-allocated work items and workspace (the allocation-free evaluate).
+
+// The kernels form a B row's offset as one 32 x 32 -> 64-bit product of the
+// row index and the leading dimension, so W's leading dimension must fit 32
+// bits (the workspace's is r plus padding).
+static void check_ldw(i64 ldw) {
+  if (ldw > (i64)UINT32_MAX) fail(GOFMM_ELIMIT, "leading dimension of W above 2^32 - 1");
+}
 static bool make_args(Compression& c, int li, int cfg, const EvalArgs& e, dev::KArgs& a, int& grid,
                       const std::pair<int2*, int>* fixed_items = nullptr, float* fixed_ws = nullptr) {
   DeviceState* d = c.dev;
@@ -476,6 +496,7 @@ static bool make_args(Compression& c, int li, int cfg, const EvalArgs& e, dev::K
   }
   a.rows = d->rows;
   a.W = e.W;
+  check_ldw(e.ldw);
   a.ldw = e.ldw;
   a.U = e.U;
   a.ldu = e.ldu;
@@ -507,6 +528,7 @@ static bool rows_vec(const float* W, i64 ldw, const float* U, i64 ldu, i64 r) {
 }
 
 static dev::BInst make_inst(Compression& c, int prec, i64 r, const float* W, i64 ldw, float* U, i64 ldu) {
+  check_ldw(ldw);
   DeviceState* d = c.dev;
   dev::BInst in;
   in.tasks = d->tasks;

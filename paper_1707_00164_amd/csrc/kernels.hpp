@@ -222,9 +222,11 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const bool ok = rb0 + i < nrb && g < kch;
-      const long long u = abase + (ok ? ((long long)(rb0 + i) * kch + g) * 64 : 0) + lane;
-      ra[slot][0][i] = Ab[u];
-      if constexpr (X3) ra[slot][1][i] = Ab[aplane + u];
+      // the chunk's start is wave-uniform (a scalar address); lanes add their
+      // own 16-byte offset
+      const auto Ac = Ab + (abase + (ok ? ((long long)(rb0 + i) * kch + g) * 64 : 0));
+      ra[slot][0][i] = Ac[lane];
+      if constexpr (X3) ra[slot][1][i] = Ac[aplane + lane];
     }
   };
 
@@ -255,7 +257,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   // coh: the slab holds workspace rows (produced by other tiles of a
   // persistent launch), read with device-coherent loads; rows of W are
   // read-only during a launch and take the cached path
-  auto bload = [&](bool coh, int set) {
+  auto bload = [&](bool coh, int set, int e0, int e1) {
     if (!bwave) return;
 #pragma unroll
     for (int t = 0; t < BST; ++t) {
@@ -265,16 +267,18 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
         const int code = nc[t][e];
         zr = code == ROW_ZERO;
         const bool inw = code >= 0;
-        const long long idx = inw ? code : -(code + 1);
-        const long long ld = inw ? a.ldw : a.ldws;
-        return (inw ? Wg : WSg) + idx * ld;
+        // row index and leading dimension both fit 32 bits (checked on the
+        // host), so the offset is one 32 x 32 -> 64-bit multiply
+        const unsigned int idx = inw ? (unsigned int)code : (unsigned int)(-(code + 1));
+        const unsigned int ld = inw ? (unsigned int)a.ldw : (unsigned int)a.ldws;
+        return (inw ? Wg : WSg) + (unsigned long long)idx * ld;
       };
       // (the row address is made opaque before the select, so the compiler
       // cannot move its computation into a branch)
       if constexpr (VEC) {                            // rows 16-byte aligned, r % 4 == 0
         const bool zc = col >= a.r;
 #pragma unroll
-        for (int e = 0; e < SBR; ++e) {
+        for (int e = e0; e < e1; ++e) {
           bool zr;
           unsigned long long pa = (unsigned long long)(rowp(e, zr) + col);
           asm volatile("" : "+v"(pa));
@@ -291,7 +295,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
         }
       } else {
 #pragma unroll
-        for (int e = 0; e < SBR; ++e) {
+        for (int e = e0; e < e1; ++e) {
           bool zr;
           unsigned long long pa = (unsigned long long)(rowp(e, zr) + col);
           asm volatile("" : "+v"(pa));
@@ -468,10 +472,10 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   }
   if (ns > 0) {
     cload(0);
-    bload(0 < td.kws, 0);
+    bload(0 < td.kws, 0, 0, SBR);
     if constexpr (DEP == 2) {
       cload(KSLAB);
-      bload(KSLAB < td.kws, 1);
+      bload(KSLAB < td.kws, 1, 0, SBR);
     }
     cload(DEP * KSLAB);
     if (act) {
@@ -479,7 +483,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       for (int s = 0; s < DEP * NS; ++s) aload(s, s);
     }
     bstore(0, 0, 4, 0);
-    bload(DEP * KSLAB < td.kws, 0);
+    bload(DEP * KSLAB < td.kws, 0, 0, SBR);
     cload((DEP + 1) * KSLAB);
     gload(0);
     gstore(0);
@@ -508,19 +512,31 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       // slab kt + 1 into the other buffer (no wave reads it before the
       // barrier below), then the B rows of slab kt + 1 + DEP and the codes of
       // the slab after; past the last slab these move data that nobody reads
-      if (s == 0) {
-        bstore(buf ^ 1, 0, 2, NXT);
-        gstore(buf ^ 1);
-      }
-      if (s == 1) {
-        bstore(buf ^ 1, 2, 4, NXT);
-        bload((kt + 1 + DEP) * KSLAB < td.kws, NXT);
-        cload((kt + 2 + DEP) * KSLAB);
-        gload(kt + 2);
+      if constexpr (F32) {
+        if (s == 0) {
+          bstore(buf ^ 1, 0, 2, NXT);
+          gstore(buf ^ 1);
+        }
+        if (s == 1) {
+          bstore(buf ^ 1, 2, 4, NXT);
+          bload((kt + 1 + DEP) * KSLAB < td.kws, NXT, 0, SBR);
+          cload((kt + 2 + DEP) * KSLAB);
+          gload(kt + 2);
+        }
+      } else {
+        // BF16 conversions and row addressing spread over all four steps
+        if (s == 0) bstore(buf ^ 1, 0, 2, NXT);
+        if (s == 1) bstore(buf ^ 1, 2, 4, NXT);
+        if (s == 2) bload((kt + 1 + DEP) * KSLAB < td.kws, NXT, 0, SBR / 2);
+        if (s == 3) {
+          bload((kt + 1 + DEP) * KSLAB < td.kws, NXT, SBR / 2, SBR);
+          cload((kt + 2 + DEP) * KSLAB);
+        }
       }
       // one matrix-core instruction at a time, with the step's LDS traffic,
       // global loads and vector work placed in its shadow
       if constexpr (F32 && ACT) interleave<TM * TN * 4, 12>();
+      if constexpr (!F32 && ACT) interleave<(X3 ? 3 : 1) * TM * TN, 8>();
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();

@@ -465,6 +465,7 @@ extern "C" int gofmm_server_submit(gofmm_server* h, int32_t model, int64_t r, co
     Model& m = *it->second;
     if (r < 1 || r > m.r_max) fail(GOFMM_EINVAL, "r must be in [1, r_max]");
     if (ldw < r || ldu < r) fail(GOFMM_EINVAL, "leading dimension smaller than r");
+    if (ldw > (int64_t)UINT32_MAX) fail(GOFMM_ELIMIT, "leading dimension of W above 2^32 - 1");
     std::unique_ptr<Request> q(new Request);
     q->id = s.next_req++;
     q->model = model;

@@ -230,6 +230,7 @@ def test_error_codes(g):
     assert b"NULL" in L.gofmm_last_error()
     assert L.gofmm_evaluate(comp.h, 4, 16, 2, 4096, 4, None) == -1     # ld < r
     assert L.gofmm_evaluate(comp.h, 4, 4096, 4, 4096 + 64, 4, None) == -1  # overlap
+    assert L.gofmm_evaluate(comp.h, 4, 4096, 1 << 32, 1 << 62, 4, None) == -7  # ldw beyond 32 bits
     with pytest.raises(g.GofmmError) as e:
         g.Compression.load("/nonexistent/file", S)
     assert e.value.code == -6
