@@ -212,10 +212,11 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   const auto Ab = gmem(reinterpret_cast<const u32x4*>(a.A));
   const long long abase = td.a_off / EPU;            // in 16-byte units
   const long long aplane = a.plane / EPU;
-  // Prefetch depth in slabs: the large BF16 tiles keep two slabs of A and of
-  // B rows in flight (their slabs are short next to memory latency); the
-  // others one.
-  constexpr int DEP = (!F32 && WM * WN == 4 && BM == 256 && BN == 128) ? 2 : 1;
+  // Prefetch depth in slabs: the large 4-wave BF16 tiles (their slabs are
+  // short next to memory latency) and the 8-wave FP32 tiles (whose second
+  // slab of registers still fits two waves per SIMD, as one block per CU
+  // already holds) keep two slabs of A and of B rows in flight; the others one.
+  constexpr int DEP = ((!F32 && WM * WN == 4 && BM == 256 && BN == 128) || (F32 && WM * WN == 8 && GEO == 0)) ? 2 : 1;
   u32x4 ra[DEP * NS][NPL][TM];
   auto aload = [&](int slot, int g) {
     if constexpr (GEO != 0) return;
