@@ -218,10 +218,12 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   // already holds) keep two slabs of A and of B rows in flight; the others one.
   constexpr int DEP = ((!F32 && WM * WN == 4 && BM == 256 && BN == 128) || (F32 && WM * WN == 8 && GEO == 0)) ? 2 : 1;
   u32x4 ra[DEP * NS][NPL][TM];
-  auto aload = [&](int slot, int g) {
+  // (TMA: the row blocks the wave computes, a compile-time count)
+  auto aload = [&](int slot, int g, auto tmac) {
+    constexpr int TMA = decltype(tmac)::value;
     if constexpr (GEO != 0) return;
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
+    for (int i = 0; i < TMA; ++i) {
       const bool ok = rb0 + i < nrb && g < kch;
       // the chunk's start is wave-uniform (a scalar address); lanes add their
       // own 16-byte offset
@@ -403,7 +405,8 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       }
     }
   };
-  auto mfma_step = [&](int s, int bs) {
+  auto mfma_step = [&](int s, int bs, auto tmac) {
+    constexpr int TMA = decltype(tmac)::value;
     if constexpr (F32) {
       // (whole vectors are reinterpreted before indexing: a bit cast of a
       // single vector element reads element 0 with this compiler)
@@ -418,7 +421,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TMA; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][q], bv[j][q], acc[i][j], 0, 0, 0);
@@ -430,7 +433,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
 #pragma unroll
       for (int pr = 0; pr < NPROD; ++pr)
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TMA; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j) {
             const int pa = (X3 && pr == 0) ? NPL - 1 : 0;    // lo*hi, hi*lo, hi*hi
@@ -445,14 +448,19 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
   const int ns = td.lda / KSLAB;                     // k is padded to whole slabs
   // slab j's A fragments sit in ring slots (j % DEP) * NS + step, its B rows
   // in register set j % DEP
-  // In the 8-wave shapes (two waves per SIMD) a wave whose rows all lie past
-  // the task's m, or whose columns all lie past r, has no products to form:
-  // it still stages its share of B and meets every barrier, but loads no A
-  // and issues no matrix-core work, so its SIMD partner has the matrix cores
-  // to itself.  (The 4-wave shapes keep one k loop: a second copy costs them
-  // registers, and an idle wave there would only leave its SIMD idle.)
+  // In the 8-wave shapes (two waves per SIMD) a wave computes only its row
+  // blocks that hold rows of the task: one whose rows all lie past the
+  // task's m, or whose columns all lie past r, has no products to form (it
+  // still stages its share of B and meets every barrier, but loads no A and
+  // issues no matrix-core work), and one whose last row block lies past m
+  // skips that block's A loads and products; either way its SIMD partner
+  // gets the matrix cores the more.  (The 4-wave shapes keep one k loop: a
+  // second copy costs them registers, and an idle wave there would only
+  // leave its SIMD idle.)
   constexpr bool IDLE = WM * WN == 8;
-  const bool act = !IDLE || __builtin_amdgcn_readfirstlane((rb0 < nrb && n0 + wc * WTN < a.r) ? 1 : 0) != 0;
+  const int tma = !IDLE ? TM
+                        : __builtin_amdgcn_readfirstlane(n0 + wc * WTN < a.r ? max(0, min(TM, nrb - rb0)) : 0);
+  const bool act = tma > 0;
   if constexpr (GEO != 0) {
     static_assert(F32 && DEP == 1, "geometric mode is FP32");
     const auto Pp = gmem(reinterpret_cast<const f32x4*>(a.gpts));
@@ -481,7 +489,7 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
     cload(DEP * KSLAB);
     if (act) {
 #pragma unroll
-      for (int s = 0; s < DEP * NS; ++s) aload(s, s);
+      for (int s = 0; s < DEP * NS; ++s) aload(s, s, std::integral_constant<int, TM>());
     }
     bstore(0, 0, 4, 0);
     bload(DEP * KSLAB < td.kws, 0, 0, SBR);
@@ -491,10 +499,11 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
     gload(1);
   }
   __syncthreads();
-  auto iter = [&](int kt, auto setc, auto actc) {
+  auto iter = [&](int kt, auto setc, auto tmac) {
     constexpr int SET = decltype(setc)::value;       // kt % DEP
     constexpr int NXT = DEP == 2 ? 1 - SET : 0;      // register set of slabs kt + 1 and kt + 1 + DEP
-    constexpr bool ACT = decltype(actc)::value;
+    constexpr int TMA = decltype(tmac)::value;       // row blocks computed
+    constexpr bool ACT = TMA > 0;
     const int buf = kt & 1;
     if constexpr (ACT) {
       bread(0, buf, 0);
@@ -507,8 +516,8 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
           bread((s + 1) & 1, buf, s + 1);
           gcomp((s + 1) & 1, buf, s + 1);
         }
-        mfma_step(SET * NS + s, s & 1);
-        aload(SET * NS + s, (kt + DEP) * NS + s);
+        mfma_step(SET * NS + s, s & 1, tmac);
+        aload(SET * NS + s, (kt + DEP) * NS + s, tmac);
       }
       // slab kt + 1 into the other buffer (no wave reads it before the
       // barrier below), then the B rows of slab kt + 1 + DEP and the codes of
@@ -536,29 +545,31 @@ __device__ __forceinline__ void tile_body(const KArgs& a, const TaskDesc& td, in
       }
       // one matrix-core instruction at a time, with the step's LDS traffic,
       // global loads and vector work placed in its shadow
-      if constexpr (F32 && ACT) interleave<TM * TN * 4, 12>();
-      if constexpr (!F32 && ACT) interleave<(X3 ? 3 : 1) * TM * TN, 8>();
+      if constexpr (F32 && ACT) interleave<TMA * TN * 4, 12>();
+      if constexpr (!F32 && ACT) interleave<(X3 ? 3 : 1) * TMA * TN, 8>();
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
   };
-  auto kloop = [&](auto actc) {
+  auto kloop = [&](auto tmac) {
     if constexpr (DEP == 1) {
-      for (int kt = 0; kt < ns; ++kt) iter(kt, std::integral_constant<int, 0>(), actc);
+      for (int kt = 0; kt < ns; ++kt) iter(kt, std::integral_constant<int, 0>(), tmac);
     } else {
       int kt = 0;
       for (; kt + 1 < ns; kt += 2) {
-        iter(kt, std::integral_constant<int, 0>(), actc);
-        iter(kt + 1, std::integral_constant<int, 1>(), actc);
+        iter(kt, std::integral_constant<int, 0>(), tmac);
+        iter(kt + 1, std::integral_constant<int, 1>(), tmac);
       }
-      if (kt < ns) iter(kt, std::integral_constant<int, 0>(), actc);
+      if (kt < ns) iter(kt, std::integral_constant<int, 0>(), tmac);
     }
   };
   if constexpr (!IDLE) {
-    kloop(std::true_type());
+    kloop(std::integral_constant<int, TM>());
   } else {
-    if (act) kloop(std::true_type());
-    else kloop(std::false_type());
+    static_assert(TM <= 2, "8-wave shapes hold one or two row blocks per wave");
+    if (tma >= TM) kloop(std::integral_constant<int, TM>());
+    else if (TM == 2 && tma == 1) kloop(std::integral_constant<int, 1>());
+    else kloop(std::integral_constant<int, 0>());
   }
 
   // epilogue: accumulator (i, j, v) of lane (li, lh) is row 8(v/4) + 4 lh + v%4,
